@@ -1,0 +1,528 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula: each compares it with a
+closed form, an invariant, a hand-derived worked instance (tests/golden), a
+textbook routine, or brute force.  CPU only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import formats
+from oracle import gleanvec as G
+from oracle.rng import SplitMix64, sample_without_replacement
+
+RNG = np.random.default_rng(12345)
+
+
+def _lowrank_data(rng, n, D, rank_scale=1.0, mean=None):
+    """Anisotropic Gaussian rows with a decaying spectrum (full rank)."""
+    lam = 1.0 / np.arange(1, D + 1)
+    R, _ = np.linalg.qr(rng.standard_normal((D, D)))
+    X = (rng.standard_normal((n, D)) * np.sqrt(lam)) @ R.T * rank_scale
+    if mean is not None:
+        X = X + mean
+    return X
+
+
+# ----------------------------------------------------------------------------- RNG
+
+def test_splitmix64_published_vectors(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "splitmix64.json")))
+    for v in g["vectors"]:
+        gen = SplitMix64(v["seed"])
+        if "outputs_hex" in v:
+            assert [gen.next() for _ in v["outputs_hex"]] == [int(h, 16) for h in v["outputs_hex"]]
+        else:
+            assert [gen.next() for _ in v["outputs"]] == v["outputs"]
+
+
+def test_sample_without_replacement():
+    gen = SplitMix64(7)
+    s = sample_without_replacement(gen, 1000, 300)
+    assert s.size == 300 and np.unique(s).size == 300 and s.min() >= 0 and s.max() < 1000
+    assert np.all(np.diff(s) > 0)
+    # every row equally likely: over many seeds the inclusion counts are flat
+    counts = np.zeros(50)
+    for seed in range(400):
+        counts[sample_without_replacement(SplitMix64(seed), 50, 10)] += 1
+    assert abs(counts.mean() - 80.0) < 1e-9 and counts.std() < 15
+    assert np.array_equal(sample_without_replacement(SplitMix64(1), 10, 20), np.arange(10))
+
+
+# ----------------------------------------------------------------------------- formats (T18)
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp8"])
+def test_format_reference_values(golden_dir, fmt):
+    g = json.load(open(os.path.join(golden_dir, "formats.json")))
+    for code, val in g[fmt]:
+        assert formats.decode(fmt, int(code, 16)) == val
+        assert formats.round_to(fmt, val) == val
+    if fmt == "fp8":
+        for code in g["fp8_nan"]:
+            assert np.isnan(formats.decode("fp8", int(code, 16)))
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp8"])
+def test_format_exhaustive_rne(fmt):
+    """Every finite code is a fixed point; every midpoint between neighbours rounds
+    to the neighbour with an even code; anything beyond max finite saturates."""
+    nbits = 8 if fmt == "fp8" else 16
+    codes = np.arange(1 << nbits)
+    vals = formats.decode(fmt, codes)
+    pos = codes[(vals > 0) & np.isfinite(vals) & ((codes >> (nbits - 1)) == 0)]
+    pv = formats.decode(fmt, pos)
+    order = np.argsort(pv)
+    pos, pv = pos[order], pv[order]
+    assert np.all(np.diff(pv) > 0)
+    assert np.array_equal(formats.round_to(fmt, pv), pv)
+    assert np.array_equal(formats.round_to(fmt, -pv), -pv)
+    mid = 0.5 * (pv[:-1] + pv[1:])
+    even = np.where(pos[:-1] % 2 == 0, pv[:-1], pv[1:])
+    assert np.array_equal(formats.round_to(fmt, mid), even)
+    # just off the midpoint goes to the nearer neighbour
+    lo = mid - (pv[1:] - pv[:-1]) * 1e-3
+    hi = mid + (pv[1:] - pv[:-1]) * 1e-3
+    assert np.array_equal(formats.round_to(fmt, lo), pv[:-1])
+    assert np.array_equal(formats.round_to(fmt, hi), pv[1:])
+    # smallest subnormal: half of it ties to zero (even), above half goes up
+    tiny = pv[0]
+    assert formats.round_to(fmt, 0.5 * tiny) == 0.0
+    assert formats.round_to(fmt, 0.75 * tiny) == tiny
+    vmax = pv[-1]
+    assert formats.SPECS[fmt][3] == vmax
+    assert formats.round_to(fmt, vmax * 4) == vmax
+    assert formats.round_to(fmt, -vmax * 4) == -vmax
+
+
+def test_format_cross_check_numpy_fp16():
+    x = RNG.standard_normal(200_000) * np.exp(RNG.uniform(-20, 12, 200_000))
+    x = x[np.abs(x) < 65504]
+    assert np.array_equal(formats.round_to("fp16", x), x.astype(np.float16).astype(np.float64))
+
+
+def test_pow2_scale():
+    for fmt, T in (("fp8", 448.0), ("fp16", 65504.0), ("bf16", 1.0)):
+        amax = np.exp(RNG.uniform(-30, 30, 5000))
+        amax = np.concatenate([amax, [T, T * 2, T / 2, T * 2 ** -10, T * 1.0000001]])
+        s = formats.pow2_scale(fmt, amax)
+        lg = np.log2(s)
+        assert np.array_equal(lg, np.round(lg))
+        r = amax / s
+        assert np.all(r <= T) and np.all(r > T / 2)
+    assert formats.pow2_scale("fp8", 0.0) == 1.0
+    assert formats.pow2_scale("fp32", 123.0) == 1.0
+
+
+# ----------------------------------------------------------------------------- top-k (T13)
+
+def test_topk_brute_force_with_ties():
+    rng = np.random.default_rng(3)
+    for trial in range(200):
+        n = int(rng.integers(1, 40))
+        k = int(rng.integers(1, n + 1))
+        sc = rng.integers(-3, 4, n).astype(np.float64)   # many exact ties
+        ids = rng.permutation(1000)[:n]
+        got_ids, got_sc = G.topk(sc, ids, k)
+        # brute force: repeatedly pick the best remaining by (score, then smaller id)
+        rem = list(zip(sc.tolist(), ids.tolist()))
+        want = []
+        for _ in range(k):
+            best = None
+            for p in rem:
+                if best is None or p[0] > best[0] or (p[0] == best[0] and p[1] < best[1]):
+                    best = p
+            want.append(best)
+            rem.remove(best)
+        assert got_ids.tolist() == [w[1] for w in want]
+        assert got_sc.tolist() == [w[0] for w in want]
+        # the definition of N (Section 2): every kept score >= every dropped score
+        kept = set(got_ids.tolist())
+        dropped = [s for s, i in zip(sc, ids) if i not in kept]
+        if dropped:
+            assert got_sc.min() >= max(dropped)
+
+
+def test_exact_topk_streamed_vs_brute():
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((3000, 16)).astype(np.float32)
+    Q = rng.standard_normal((5, 16)).astype(np.float32)
+    ids, sc = G.exact_topk(X, Q, 10, chunk=256)
+    for qi in range(5):
+        full = X.astype(np.float64) @ Q[qi].astype(np.float64)
+        want = sorted(range(3000), key=lambda i: (-full[i], i))[:10]
+        assert ids[qi].tolist() == want
+
+
+def test_recall_metric():
+    truth = np.array([[1, 2, 3, 4, 5, 6, 7, 8, 9, 10]])
+    assert G.recall(truth, truth) == 1.0
+    assert G.recall(np.array([[1, 2, 3, 4, 5, 60, 70, 80, 90, 100]]), truth) == 0.5
+
+
+# ----------------------------------------------------------------------------- k-means (T11, T12)
+
+def test_kmeans_circle_golden(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "kmeans_circle.json")))
+    ang = np.deg2rad(g["points_deg"])
+    X = np.stack([np.cos(ang), np.sin(ang)], 1)
+    a0 = np.deg2rad(g["init_deg"])
+    mu0 = np.stack([np.cos(a0), np.sin(a0)], 1)
+    mu, a, it = G.spherical_kmeans(X, mu0)
+    ac = np.deg2rad(g["centres_deg"])
+    assert np.allclose(mu, np.stack([np.cos(ac), np.sin(ac)], 1), atol=1e-15)
+    assert a.tolist() == g["assignment"]
+
+
+def test_tag_rule_equivalences():
+    """T11: for unit landmarks, argmax <x, mu> = argmax <x/|x|, mu> = argmin |x - mu|
+    (the VQ-VAE form of Section 4.2)."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((2000, 24)) * rng.uniform(0.1, 10, (2000, 1))
+    mu = G.normalise_rows(rng.standard_normal((7, 24)))
+    a1 = G.assign(X, mu)
+    a2 = G.assign(G.normalise_rows(X), mu)
+    a3 = np.argmin(((X[:, None, :] - mu[None]) ** 2).sum(-1), axis=1)
+    assert np.array_equal(a1, a2) and np.array_equal(a1, a3)
+    # lowest index on exact ties
+    mu2 = np.vstack([mu[:1], mu[:1], mu[1:]])
+    assert np.all(G.assign(X, mu2) != 1)
+
+
+def test_kmeans_monotone_and_fixed_point():
+    """T12: the Appendix A objective never decreases over EM steps; at convergence the
+    assignment is the arg-max and each centre is its members' normalised mean."""
+    rng = np.random.default_rng(6)
+    centres = G.normalise_rows(rng.standard_normal((6, 32)))
+    X = centres[rng.integers(0, 6, 3000)] + 0.35 * rng.standard_normal((3000, 32)) / np.sqrt(32)
+    Xt = G.normalise_rows(X)
+    mu = G.kmeanspp(Xt, 6, SplitMix64(11))
+    objs = [G.kmeans_objective(Xt, mu)]
+    for _ in range(30):
+        mu, a, it = G.spherical_kmeans(Xt, mu, max_iter=1)
+        objs.append(G.kmeans_objective(Xt, mu))
+    assert np.all(np.diff(objs) >= -1e-9)
+    mu, a, it = G.spherical_kmeans(Xt, mu)
+    assert np.array_equal(a, G.assign(Xt, mu))
+    for c in range(6):
+        s = Xt[a == c].sum(0)
+        assert np.allclose(mu[c], s / np.linalg.norm(s), atol=1e-14)
+    # recovery of the planted directions (well separated mixture)
+    cos = np.max(np.abs(mu @ centres.T), axis=0)
+    assert np.all(cos > 0.99)
+
+
+def test_kmeanspp_draws_far_points():
+    """k-means++ with C equal to the number of distinct points picks each exactly once
+    (a point at chord distance 0 has zero probability)."""
+    P = G.normalise_rows(np.eye(5) + 0.01)
+    X = np.repeat(P, 40, axis=0)
+    for seed in range(20):
+        mu = G.kmeanspp(X, 5, SplitMix64(seed))
+        assert np.unique(np.round(mu, 12), axis=0).shape[0] == 5
+
+
+# ----------------------------------------------------------------------------- sphering (T1-T10, T14-T16)
+
+def _fitdata(seed, n=600, m=400, D=12):
+    rng = np.random.default_rng(seed)
+    X = _lowrank_data(rng, n, D)
+    Q = _lowrank_data(rng, m, D)
+    return Q, X
+
+
+def test_golden_2d_query_aware(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "sphering_2d.json")))
+    X = np.array(g["X"]); Q = np.array(g["Q"])
+    KQ = G.second_moment(Q, mean=True)
+    W, Wp, lamQ = G.sphering_W(KQ)
+    assert np.allclose(W, g["W"], atol=1e-15)
+    assert np.allclose(lamQ, g["eig_KQ"], atol=1e-15)
+    P, lam = G.sphering_projection(W, G.second_moment(X, mean=False), g["d"])
+    assert np.allclose(lam, g["eig_WKW"], atol=1e-14)
+    A, B = P @ Wp, P @ W
+    assert np.allclose(A, g["A"], atol=1e-15) and np.allclose(B, g["B"], atol=1e-15)
+    assert np.allclose(A.T @ B, g["AtB"], atol=1e-15)
+    L, _, _ = G.loss_pairwise(A[None], B[None], Q, [X], n_pairs=1.0)
+    assert abs(L - g["loss_sum"]) < 1e-13
+    L, _, _ = G.loss_pairwise(A[None], B[None], Q, [X])
+    assert abs(L - g["loss_mean"]) < 1e-13
+    U, _, _ = np.linalg.svd(X.T)
+    pca = U[:, :1].T
+    L, _, _ = G.loss_pairwise(pca[None], pca[None], Q, [X], n_pairs=1.0)
+    assert abs(L - g["pca_loss_sum"]) < 1e-12
+
+
+def test_T1_W_is_psd_root():
+    Q, X = _fitdata(1)
+    KQ = G.second_moment(Q, mean=True)
+    W, Wp, _ = G.sphering_W(KQ)
+    assert np.allclose(W, W.T, atol=1e-14)
+    assert np.linalg.eigvalsh(W).min() > 0
+    assert np.allclose(W @ W, KQ, atol=1e-13 * np.abs(KQ).max())
+    assert np.allclose(W @ Wp, np.eye(12), atol=1e-11)
+    # Eq. 6: Q Q^T = U S^2 U^T from the SVD of the stacked queries
+    U, S, _ = np.linalg.svd(Q.T / np.sqrt(Q.shape[0]), full_matrices=False)
+    assert np.allclose((U * S) @ U.T, W, atol=1e-12)
+
+
+def test_T2_sphered_queries_are_white():
+    Q, X = _fitdata(2)
+    for d in (3, 7, 12):
+        A, B = G.leanvec_sphering(Q, X, d)
+        Z = Q @ A.T
+        assert np.allclose(Z.T @ Z / Q.shape[0], np.eye(d), atol=1e-11)
+
+
+def test_T3_reduced_database_moment_is_diagonal():
+    Q, X = _fitdata(3)
+    KQ = G.second_moment(Q, mean=True)
+    W, Wp, _ = G.sphering_W(KQ)
+    KX = G.second_moment(X, mean=False)
+    P, lam = G.sphering_projection(W, KX, 5)
+    B = P @ W
+    Y = (X @ B.T).T @ (X @ B.T)
+    assert np.allclose(Y, np.diag(lam[:5]), atol=1e-10 * lam[0])
+
+
+def test_T4_full_dimension_is_exact():
+    Q, X = _fitdata(4)
+    A, B = G.leanvec_sphering(Q, X, 12)
+    assert np.allclose(A.T @ B, np.eye(12), atol=1e-11)
+    assert np.allclose((Q @ A.T) @ (X @ B.T).T, Q @ X.T, atol=1e-10)
+
+
+def test_T5_T6_T7_loss_closed_form_gradient_zero_and_gram():
+    """T5: the loss at the sphering solution is the Eckart-Young tail of W K_X W (with
+    W from the summed K_Q); T6: its gradient vanishes (global minimiser of Problem 3
+    over rank-d A^T B, by Eq. 5); T7: pairwise loss = Gram loss of Eq. 5."""
+    rng = np.random.default_rng(7)
+    D, d, C = 10, 4, 3
+    Q = _lowrank_data(rng, 300, D)
+    Xs = [_lowrank_data(rng, 200 + 50 * c, D, mean=rng.standard_normal(D)) for c in range(C)]
+    KQs = G.second_moment(Q, mean=False)
+    Ws, _, _ = G.sphering_W(KQs)
+    A = np.empty((C, d, D)); B = np.empty((C, d, D))
+    tail = 0.0
+    for c in range(C):
+        A[c], B[c] = G.leanvec_sphering(Q, Xs[c], d)
+        lam = np.linalg.eigvalsh(Ws @ G.second_moment(Xs[c], False) @ Ws)
+        tail += np.sort(lam)[::-1][d:].sum()
+    L, dA, dB = G.loss_pairwise(A, B, Q, Xs, n_pairs=1.0)
+    assert abs(L - tail) < 1e-9 * tail
+    # gradient ~ 0 at the optimum, relative to the gradient at a perturbed point
+    L2, dA2, dB2 = G.loss_pairwise(A + 0.01 * rng.standard_normal(A.shape), B, Q, Xs, n_pairs=1.0)
+    assert np.linalg.norm(dA) < 1e-9 * np.linalg.norm(dA2)
+    assert np.linalg.norm(dB) < 1e-9 * np.linalg.norm(dA2)
+    # pairwise == Gram at a random point
+    Ar = rng.standard_normal(A.shape); Br = rng.standard_normal(B.shape)
+    KX = np.stack([G.second_moment(x, False) for x in Xs])
+    N = Q.shape[0] * sum(x.shape[0] for x in Xs)
+    Lp, dAp, dBp = G.loss_pairwise(Ar, Br, Q, Xs)
+    Lg, dAg, dBg = G.loss_gram(Ar, Br, KQs, KX, N)
+    assert abs(Lp - Lg) < 1e-12 * Lp
+    assert np.allclose(dAp, dAg, rtol=1e-10, atol=1e-12 * np.abs(dAp).max())
+    assert np.allclose(dBp, dBg, rtol=1e-10, atol=1e-12 * np.abs(dBp).max())
+
+
+def test_T17_gradient_matches_central_differences():
+    """The loss is quadratic in any single entry of A_c or B_c, so a central difference
+    equals the derivative up to rounding for any step h."""
+    rng = np.random.default_rng(8)
+    D, d = 6, 3
+    Q = rng.standard_normal((40, D))
+    Xs = [rng.standard_normal((30, D)), rng.standard_normal((25, D))]
+    A = rng.standard_normal((2, d, D)); B = rng.standard_normal((2, d, D))
+    _, dA, dB = G.loss_pairwise(A, B, Q, Xs)
+    h = 1e-3
+    for (arr, grad) in ((A, dA), (B, dB)):
+        for idx in [(0, 0, 0), (1, 2, 5), (0, 1, 3), (1, 0, 1)]:
+            ap = arr.copy(); ap[idx] += h
+            am = arr.copy(); am[idx] -= h
+            args_p = (ap, B) if arr is A else (A, ap)
+            args_m = (am, B) if arr is A else (A, am)
+            fd = (G.loss_pairwise(*args_p, Q, Xs)[0] - G.loss_pairwise(*args_m, Q, Xs)[0]) / (2 * h)
+            assert abs(fd - grad[idx]) < 1e-8 * max(1.0, abs(grad[idx]))
+
+
+def test_T8_svd_route_equals_eigen_route():
+    """Algorithm 2 as printed (SVD of Q, then SVD of W X) gives the same A^T B as the
+    eigen route of Section 3.2."""
+    Q, X = _fitdata(9)
+    d = 5
+    U, S, _ = np.linalg.svd(Q.T / np.sqrt(Q.shape[0]), full_matrices=False)
+    W = (U * S) @ U.T
+    Ux, _, _ = np.linalg.svd(W @ X.T, full_matrices=False)
+    P = Ux[:, :d].T
+    A1, B1 = P @ np.linalg.inv(W), P @ W
+    A2, B2 = G.leanvec_sphering(Q, X, d)
+    assert np.allclose(A1.T @ B1, A2.T @ B2, atol=1e-10)
+    # and the same rows up to sign
+    assert np.allclose(np.abs(A1), np.abs(A2), atol=1e-9)
+
+
+def test_T10_isotropic_queries_reduce_to_pca():
+    """With K_Q = alpha I, W = sqrt(alpha) I and A, B are (scaled) top-d left singular
+    vectors of X: a truncated uncentered PCA."""
+    rng = np.random.default_rng(10)
+    D, d = 9, 4
+    X = _lowrank_data(rng, 500, D)
+    Q = np.sqrt(2.5 * D) * np.eye(D)            # K_Q (mean) = 2.5 I
+    A, B = G.leanvec_sphering(Q, X, d)
+    U, _, _ = np.linalg.svd(X.T, full_matrices=False)
+    proj = U[:, :d] @ U[:, :d].T
+    assert np.allclose(A.T @ B, proj, atol=1e-12)
+    assert np.allclose(B / np.sqrt(2.5), A * np.sqrt(2.5), atol=1e-12)
+
+
+def test_T14_scale_invariance():
+    Q, X = _fitdata(11)
+    A1, B1 = G.leanvec_sphering(Q, X, 5)
+    A2, B2 = G.leanvec_sphering(Q * 7.0, X, 5)
+    assert np.allclose(A1.T @ B1, A2.T @ B2, atol=1e-11)
+    assert np.allclose(A2 * 7.0, A1, atol=1e-11)
+
+
+def test_T15_pseudo_inverse_projects_on_query_span():
+    rng = np.random.default_rng(12)
+    D = 10
+    Q = rng.standard_normal((6, D))        # rank 6 < D
+    X = _lowrank_data(rng, 300, D)
+    A, B = G.leanvec_sphering(Q, X, D)
+    Pi = Q.T @ np.linalg.pinv(Q.T)         # projector onto span of the queries
+    assert np.allclose(A.T @ B, Pi, atol=1e-10)
+    q = rng.standard_normal(6) @ Q         # any query in the span is exact
+    x = rng.standard_normal(D)
+    assert abs((A @ q) @ (B @ x) - q @ x) < 1e-10 * np.linalg.norm(q) * np.linalg.norm(x)
+
+
+def test_T16_nested_target_dimensions():
+    """Section 3.1: the first d' rows of the d-solution are the d'-solution."""
+    Q, X = _fitdata(13)
+    A8, B8 = G.leanvec_sphering(Q, X, 8)
+    A3, B3 = G.leanvec_sphering(Q, X, 3)
+    assert np.allclose(A8[:3], A3, atol=1e-11) and np.allclose(B8[:3], B3, atol=1e-11)
+
+
+def test_T9_one_cluster_is_leanvec_sphering():
+    Q, X = _fitdata(14, n=900)
+    m = G.fit(X, Q, 4, 1, seed=3)
+    A, B = G.leanvec_sphering(Q, X, 4)
+    assert np.allclose(m.A[0], A, atol=1e-12) and np.allclose(m.B[0], B, atol=1e-12)
+    assert np.allclose(np.linalg.norm(m.mu, axis=1), 1.0)
+
+
+def test_fit_gleanvec_properties():
+    """Algorithm 5 end to end: unit landmarks, per-cluster sphering, and a loss no larger
+    than the single-projection (C = 1) solution on the learn data."""
+    rng = np.random.default_rng(15)
+    D, d, C = 16, 4, 3
+    means = G.normalise_rows(rng.standard_normal((C, D))) * 3
+    X = np.concatenate([_lowrank_data(rng, 400, D, mean=means[c]) for c in range(C)])
+    Q = _lowrank_data(rng, 500, D)
+    m = G.fit(X, Q, d, C, seed=5)
+    assert np.allclose(np.linalg.norm(m.mu, axis=1), 1.0)
+    assert m.counts.sum() == X.shape[0] and not m.fallback.any()
+    tags = G.assign(X, m.mu)
+    Xs = [X[tags == c] for c in range(C)]
+    Lg, _, _ = G.loss_pairwise(m.A, m.B, Q, Xs)
+    m1 = G.fit(X, Q, d, 1, seed=5)
+    L1, _, _ = G.loss_pairwise(m1.A, m1.B, Q, [X])
+    assert Lg <= L1 * (1 + 1e-12)
+    # each cluster's projection is the sphering solution of its own member set (T2 holds)
+    for c in range(C):
+        Z = Q @ m.A[c].T
+        assert np.allclose(Z.T @ Z / Q.shape[0], np.eye(d), atol=1e-10)
+
+
+def test_fit_fallback_for_tiny_cluster():
+    rng = np.random.default_rng(16)
+    D, d = 8, 5
+    X = np.concatenate([_lowrank_data(rng, 300, D, mean=3 * np.eye(D)[0]),
+                        3 * np.eye(D)[1] + 0.01 * rng.standard_normal((3, D))])
+    Q = _lowrank_data(rng, 200, D)
+    mu0 = np.stack([np.eye(D)[0], np.eye(D)[1]])
+    m = G.fit(X, Q, d, 2, seed=1, mu0=mu0)
+    assert m.counts.tolist() == [300, 3] and m.fallback.tolist() == [False, True]
+    A, B = G.leanvec_sphering(Q, X, d)
+    assert np.allclose(m.A[1], A, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------- encode and search
+
+def _small_problem(fmt, seed=20, n=3000, D=24, d=8, C=4, m=7):
+    rng = np.random.default_rng(seed)
+    means = G.normalise_rows(rng.standard_normal((C, D))) * 2
+    X = np.concatenate([_lowrank_data(rng, n // C, D, mean=means[c]) for c in range(C)]).astype(np.float32)
+    Q = _lowrank_data(rng, m, D).astype(np.float32)
+    QL = _lowrank_data(rng, 400, D).astype(np.float32)
+    model = G.fit(X, QL, d, C, seed=2)
+    return model, X, Q
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "fp16", "bf16", "fp8"])
+def test_encode_definition(fmt):
+    model, X, Q = _small_problem(fmt)
+    idx = G.encode(model.mu, model.B, X, fmt)
+    n = X.shape[0]
+    # grouping: a permutation, clusters contiguous, stable (increasing ids inside)
+    assert np.array_equal(np.sort(idx.ids), np.arange(n))
+    for c in range(model.C):
+        seg = idx.ids[idx.offsets[c]:idx.offsets[c + 1]]
+        assert np.all(np.diff(seg) > 0) and np.all(idx.tags[seg] == c)
+    # brute-force per row: x_low = B_c x for c = arg-max tag, one FP32 rounding
+    for p in RNG.integers(0, n, 50):
+        i = idx.ids[p]
+        c = int(np.argmax([float(np.dot(X[i].astype(np.float64), model.mu[cc])) for cc in range(model.C)]))
+        assert idx.tags[i] == c
+        exact = np.array([sum(float(model.B[c, j, t]) * float(X[i, t]) for t in range(X.shape[1]))
+                          for j in range(model.d)])
+        assert np.allclose(idx.v[p], exact, rtol=2 ** -23, atol=0)
+        s = idx.scale[c]
+        assert np.all(np.abs(idx.xq[p] * s - idx.v[p]) <= np.abs(idx.v[p]) * (2 ** -3 if fmt == "fp8" else 2 ** -7) + s * 2 ** -6)
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "fp16", "bf16", "fp8"])
+def test_search_stages_against_brute_force(fmt):
+    model, X, Q = _small_problem(fmt, seed=21)
+    idx = G.encode(model.mu, model.B, X, fmt)
+    k, kappa = 5, 40
+    out = G.search(idx, model.A, Q, k, kappa)
+    n = X.shape[0]
+    pos_of = np.empty(n, np.int64); pos_of[idx.ids] = np.arange(n)
+    for qi in range(Q.shape[0]):
+        # reduced score of every vector by plain loops over Eq. 11 with the eager views
+        s = np.empty(n)
+        for i in range(n):
+            c = idx.tags[i]
+            p = pos_of[i]
+            s[i] = idx.scale[c] * out["t"][qi, c] * sum(out["qh"][qi, c, j] * idx.xq[p, j] for j in range(model.d))
+        want = sorted(range(n), key=lambda i: (-s[i], i))[:kappa]
+        assert out["cand_ids"][qi].tolist() == want
+        exact = {i: float(np.dot(X[i].astype(np.float64), Q[qi].astype(np.float64))) for i in want}
+        final = sorted(want, key=lambda i: (-exact[i], i))[:k]
+        assert out["ids"][qi].tolist() == final
+    # the FP32 view approximates the exact A_c q
+    qc_exact = np.einsum("cjD,mD->mcj", model.A, Q.astype(np.float64))
+    assert np.allclose(out["qc"], qc_exact, rtol=2 ** -23, atol=0)
+
+
+def test_search_full_dimension_recovers_exact_topk():
+    """T4 through the whole search: with d = D, FP32 storage and kappa = k the reduced
+    scores equal the exact inner products up to FP32 rounding, so the result is the
+    exact top-k (checked on queries whose k-th gap is wide)."""
+    rng = np.random.default_rng(22)
+    D = 16
+    X = _lowrank_data(rng, 2000, D).astype(np.float32)
+    Q = _lowrank_data(rng, 20, D).astype(np.float32)
+    model = G.fit(X, _lowrank_data(rng, 300, D), D, 1, seed=4)
+    idx = G.encode(model.mu, model.B, X, "fp32")
+    out = G.search(idx, model.A, Q, 10, 10)
+    gt, gs = G.exact_topk(X, Q, 11)
+    for qi in range(Q.shape[0]):
+        if gs[qi, 9] - gs[qi, 10] > 1e-4 * abs(gs[qi, 0]):
+            assert set(out["ids"][qi].tolist()) == set(gt[qi, :10].tolist())
+        assert np.allclose(out["cand_scores"][qi], np.sort(out["out_scores"][qi])[::-1], rtol=1e-5, atol=1e-5)
