@@ -1,0 +1,234 @@
+"""Benchmark of the GleanVec search path on one MI355X.
+
+Workload (default): n = 10M database vectors, D = 768 -> d = 160, C = 32
+clusters, kappa = 200, k = 10 -- the shape of the paper's largest OOD set
+(RQA-10M-OOD, Table 1) -- drawn from a seeded 32-component Gaussian mixture
+with decaying spectra and OOD queries (shifted means, rotated covariance).
+
+A step is one query batch through the whole search path (S1 projection, S2/S3
+scoring with top-kappa, merge, S4 rerank) against the index resident in HBM.
+The index build (fit, encode) runs once before timing and is reported
+separately.  Prints one JSON line (rank 0, N = 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QPS at 10-recall@10≥0.9, 10M×768→160, C=32; achieved HBM GB/s vs peak"
+PEAK = {"hbm_gbs": 8000.0, "fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}  # TFLOP/s
+BYTES = {"fp32": 4, "fp16": 2, "bf16": 2, "fp8": 1}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mix32-10m-d768")
+    ap.add_argument("--n", type=int, default=0, help="override database size (debug)")
+    ap.add_argument("--fmt", default="fp16")
+    ap.add_argument("--m", type=int, default=4096)
+    ap.add_argument("--sweep", action="store_true", help="also time every format at m = 1, 64, 4096")
+    ap.add_argument("--single-queries", type=int, default=200)
+    ap.add_argument("--recall-queries", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=1_000_000)
+    ap.add_argument("--cpu-queries", type=int, default=32)
+    return ap.parse_args()
+
+
+def exact_topk_device(X, Q, k, chunk=1 << 18):
+    """Exact top-k by FP64 inner product on the device (recall ground truth)."""
+    import torch
+    Q64 = Q.double()
+    best_s = torch.full((Q.shape[0], 0), -float("inf"), dtype=torch.float64, device=Q.device)
+    best_i = torch.zeros((Q.shape[0], 0), dtype=torch.int64, device=Q.device)
+    for s in range(0, X.shape[0], chunk):
+        S = Q64 @ X[s:s + chunk].double().T
+        v, i = torch.topk(S, min(k, S.shape[1]), dim=1)
+        allv = torch.cat([best_s, v], 1)
+        alli = torch.cat([best_i, i + s], 1)
+        v2, j = torch.topk(allv, k, dim=1)
+        best_s, best_i = v2, torch.gather(alli, 1, j)
+    return best_i.cpu().numpy()
+
+
+def recall(found, truth, K=10):
+    return float(np.mean([len(set(f[:K].tolist()) & set(g[:K].tolist())) / K for f, g in zip(found, truth)]))
+
+
+def time_search(gv, model, index, Qpool, m, k, kappa, steps, warmup, profile=True):
+    """Wall-clock time of `steps` batches of m queries (rotating through the pool)."""
+    import torch
+    nb = max(1, Qpool.shape[0] // m)
+    batches = [Qpool[(i % nb) * m:(i % nb) * m + m] for i in range(nb)]
+    for i in range(warmup):
+        gv.search(model, index, batches[i % nb], k, kappa)
+    torch.cuda.synchronize()
+    gv.profile_read()
+    if profile:
+        gv.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        gv.search(model, index, batches[i % nb], k, kappa)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gv.profile_enable(False)
+    ms_s, n_s, ms_m, n_m = gv.profile_read()
+    return dt, (ms_s / max(n_s, 1)), (ms_m / max(n_m, 1))
+
+
+def cpu_baseline(X, geom, wl, m_s, n_s):
+    """The FP64 oracle's search (S1-S4) on a bounded sample, scaled to the full n."""
+    from threadpoolctl import threadpool_info
+    from oracle import gleanvec as G
+    import synth
+    n_s = min(n_s, X.shape[0])
+    Xs = X[:n_s].cpu().numpy()
+    QL = synth.queries(geom, 2000, synth.S_QLEARN)
+    om = G.fit(Xs[:20000], QL, wl.d, wl.C, seed=5, max_iter=10)
+    oi = G.encode(om.mu, om.B, Xs, "fp16")
+    Q = synth.queries(geom, m_s, synth.S_QTEST)
+    t0 = time.perf_counter()
+    G.search(oi, om.A, Q, wl.k, wl.kappa)
+    dt = time.perf_counter() - t0
+    per_query_full = dt / m_s * (wl.n / n_s)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": 1.0 / per_query_full, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 oracle S1-S4 (fp16 storage) for {m_s} queries over the first {n_s} of {wl.n} rows, "
+                      f"{dt:.2f} s, scaled linearly to n = {wl.n}",
+            "nproc": os.cpu_count()}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        return 2
+    import torch
+    import synth
+    import paper_2410_22347_amd as gv
+
+    wl = synth.WORKLOADS[a.workload]
+    if a.n:
+        wl = synth.Workload(**{**wl.__dict__, "n": a.n})
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {wl.name} n={wl.n} D={wl.D} d={wl.d} C={wl.C}")
+    geom = synth.make_geometry(wl.cfg, wl.D, wl.J, wl.law)
+    t0 = time.perf_counter()
+    X = synth.draw_torch(geom, wl.n, synth.S_DB, dev)
+    QL = synth.draw_torch(geom, wl.m_learn, synth.S_QLEARN, dev, queries_=True)
+    QT = synth.draw_torch(geom, wl.m_test, synth.S_QTEST, dev, queries_=True)
+    rows = torch.from_numpy(synth.learn_rows(wl.n, synth.learn_sample_size(wl.n), wl.cfg)).to(dev)
+    XL = X[rows].contiguous()
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log(f"[bench] data drawn in {t_gen:.1f} s")
+
+    t0 = time.perf_counter()
+    model = gv.fit(XL, QL, wl.d, wl.C, seed=synth.fit_seed(wl.cfg))
+    t_fit = time.perf_counter() - t0
+    del XL
+    log(f"[bench] fit {t_fit:.1f} s")
+
+    nrq = min(a.recall_queries, QT.shape[0])
+    gt = exact_topk_device(X, QT[:nrq], wl.k)
+    log("[bench] ground truth done")
+
+    fmts = ["fp32", "fp16", "bf16", "fp8"] if a.sweep else [a.fmt]
+    if a.fmt not in fmts:
+        fmts.append(a.fmt)
+    sweep = []
+    main_rec = None
+    for fmt in fmts:
+        t0 = time.perf_counter()
+        index = gv.encode(model, X, fmt)
+        torch.cuda.synchronize()
+        t_enc = time.perf_counter() - t0
+        ids, _ = gv.search(model, index, QT[:nrq], wl.k, wl.kappa)
+        rec = recall(ids.cpu().numpy(), gt)
+        log(f"[bench] {fmt}: encode {t_enc:.2f} s, 10-recall@10 = {rec:.4f}")
+        ms_list = [a.m] if not a.sweep else sorted({1, 64, 4096, a.m})
+        for m in ms_list:
+            if m == 1:
+                steps, warm = a.single_queries, 5
+            else:
+                steps, warm = (a.steps, a.warmup) if (fmt == a.fmt and m == a.m) else (max(3, a.steps // 4), 2)
+            dt, ms_score, ms_merge = time_search(gv, model, index, QT, m, wl.k, wl.kappa, steps, warm)
+            qps = m * steps / dt
+            ent = {"fmt": fmt, "m": m, "qps": qps, "ms_per_batch": dt / steps * 1e3,
+                   "score_kernel_ms": ms_score, "merge_ms": ms_merge, "recall": rec, "encode_s": t_enc}
+            b = BYTES[fmt]
+            hbm = wl.n * wl.d * b / (ms_score * 1e-3) / 1e9
+            flops = 2.0 * m * wl.n * wl.d / (ms_score * 1e-3) / 1e12
+            ent["score_hbm_gbs"] = hbm
+            ent["score_tflops"] = flops
+            sweep.append(ent)
+            log(f"[bench]   {fmt} m={m}: {qps:,.0f} q/s, batch {dt / steps * 1e3:.3f} ms, "
+                f"score kernel {ms_score:.3f} ms ({hbm:,.0f} GB/s, {flops:,.1f} TFLOP/s), merge {ms_merge:.3f} ms")
+            if fmt == a.fmt and m == a.m:
+                main_rec = (ent, dt, steps)
+        del index
+        torch.cuda.empty_cache()
+
+    ent, dt, steps = main_rec
+    m = a.m
+    b = BYTES[a.fmt]
+    avg_s = ent["score_kernel_ms"] * 1e-3
+    if m <= 64:
+        roof = {"bound": "hbm", "achieved": wl.n * wl.d * b / avg_s / 1e9, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": 2.0 * m * wl.n * wl.d / avg_s / 1e12, "peak": PEAK[a.fmt],
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "k_score_select"
+    roof["avg_launch_ms"] = ent["score_kernel_ms"]
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(X, geom, wl, a.cpu_queries, a.cpu_rows)
+
+    out = {
+        "metric": METRIC,
+        "value": ent["qps"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16 (f32 accumulate)", "bf16": "bf16 (f32 accumulate)",
+                  "fp8": "fp8-e4m3 (f32 accumulate)"}[a.fmt],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.n, "D": wl.D, "d": wl.d, "C": wl.C, "kappa": wl.kappa,
+                   "k": wl.k, "batch": m, "storage": a.fmt},
+        "recall_at_10": ent["recall"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "build": {"datagen_s": t_gen, "fit_s": t_fit, "encode_s": ent["encode_s"]},
+        "sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

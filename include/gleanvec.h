@@ -1,0 +1,271 @@
+/*
+ * gleanvec.h -- C ABI of the MI355X (gfx950) GleanVec / LeanVec-Sphering library.
+ *
+ * The library implements the data-parallel path of GleanVec (Tepper et al.,
+ * "GleanVec: Accelerating vector search with minimalist nonlinear
+ * dimensionality reduction", arXiv 2410.22347):
+ *
+ *   fit     -- learning (Algorithm 5): spherical k-means landmarks
+ *              (Appendix A) and one LeanVec-Sphering projection pair per
+ *              cluster (Algorithm 2, through the eigendecompositions of the
+ *              second-moment statistics of Section 3.2);
+ *   encode  -- index build: cluster tags (Eq. 9) and reduced vectors
+ *              x_low = B_c x (Eq. 10), grouped by cluster and stored in FP32,
+ *              FP16, BF16 or FP8-E4M3 with a per-cluster scale;
+ *   search  -- multi-step search (Algorithm 1) with the eager inner product
+ *              (Algorithm 4) and a brute-force main step: all views
+ *              q_c = A_c q, reduced scores <q_c, x_low_i> (Eq. 11) for every
+ *              database vector, the kappa best, and a full-dimension rerank
+ *              to the final k.
+ *
+ * Conventions shared by every call:
+ *   - Array arguments marked "device" are device pointers on the current HIP
+ *     device (for instance torch tensors' data_ptr()); "host" arrays are
+ *     ordinary host memory.  Matrices are row-major and dense.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls that take a stream enqueue their device work on it and may return
+ *     before it finishes; outputs are valid once the stream has reached that
+ *     point.  Calls that return host data synchronise the stream first.
+ *   - The caller owns every input and output buffer.  Models and indices own
+ *     their device memory until the matching *_destroy call.  Models and
+ *     indices are immutable after creation, so concurrent searches on
+ *     different streams are safe.
+ *   - Every call returns a gv_status; no C++ exception or abort crosses the
+ *     ABI.  On error, output handles are set to NULL, and
+ *     gv_last_error() returns a thread-local message naming the failure.
+ */
+#ifndef GLEANVEC_H
+#define GLEANVEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GV_OK = 0,
+  GV_EINVAL = -1,        /* an argument is out of range or inconsistent */
+  GV_ENOMEM = -2,        /* device or host allocation failed */
+  GV_EDEVICE = -3,       /* a HIP runtime call failed */
+  GV_ENOTFIT = -4,       /* the handle is NULL or was not produced by this library */
+  GV_ENONFINITE = -5,    /* an input holds NaN or +-Inf */
+  GV_EUNSUPPORTED = -6   /* valid request that this build does not handle */
+} gv_status;
+
+/* Storage format of the reduced vectors (and of the query views they meet). */
+typedef enum {
+  GV_FP32 = 0,     /* IEEE binary32, no scaling */
+  GV_FP16 = 1,     /* IEEE binary16 */
+  GV_BF16 = 2,     /* bfloat16 */
+  GV_FP8_E4M3 = 3  /* OCP FP8 E4M3 (e4m3fn: no infinities, max 448) */
+} gv_format;
+
+typedef struct gv_model gv_model;
+typedef struct gv_index gv_index;
+
+/* Options of gv_fit; a NULL pointer selects every default. */
+typedef struct {
+  int32_t max_iter;        /* Lloyd steps of spherical k-means, default 50 */
+  int64_t kmeans_sample;   /* learn vectors used by k-means, default 100000 (Appendix A) */
+  const double* init_centroids; /* host C x D initial landmarks (unit rows) or NULL for k-means++ */
+} gv_fit_opts;
+
+/* ------------------------------------------------------------------ errors */
+
+/* Static string naming a status code. */
+const char* gv_status_string(gv_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char* gv_last_error(void);
+
+/* ------------------------------------------------------------------ fit */
+
+/*
+ * gv_fit -- GleanVec learning, Algorithm 5 of the paper.
+ *
+ * X_learn  device, n_learn x D FP32: learning database vectors (X_learn).
+ * Q_learn  device, m_learn x D FP32: learning queries (Q_learn).
+ * d        target dimensionality, 1 <= d <= D.
+ * C        number of clusters, 1 <= C <= 255.
+ * seed     seed of the SplitMix64 generator that draws the k-means sample
+ *          (uniform, without replacement, of min(n_learn, kmeans_sample)
+ *          rows, Appendix A) and the k-means++ seeding draws.
+ * opts     see gv_fit_opts; may be NULL.
+ *
+ * Steps, all in FP64: normalise the sample and run spherical k-means
+ * (k-means++ seeding on the squared chord distance, Lloyd steps until no
+ * assignment changes); tag every learn vector by arg-max <x, mu_c> (Eq. 9,
+ * lowest c on ties); accumulate the uncentered second moments
+ * K_Q = (1/m_learn) sum q q^T and K_{X_c} = sum_{x in X_c} x x^T
+ * (Section 3.2); W = K_Q^(1/2) with its pseudo-inverse W+ (eigenvalues below
+ * D * 2^-52 * lambda_max dropped, Section 3); for each cluster, P_c = the d
+ * leading eigenvectors of W K_{X_c} W (rows, sign-fixed so that each row's
+ * largest-magnitude entry is positive), A_c = P_c W+ and B_c = P_c W.
+ * A cluster with fewer than d learn vectors uses the projection of the pooled
+ * statistics sum_c K_{X_c}.
+ *
+ * Errors: GV_EINVAL (sizes), GV_ENONFINITE (NaN/Inf in the inputs),
+ * GV_ENOMEM, GV_EDEVICE.  Synchronises `stream` before returning.
+ */
+gv_status gv_fit(const float* X_learn, int64_t n_learn, const float* Q_learn, int64_t m_learn,
+                 int32_t D, int32_t d, int32_t C, uint64_t seed, const gv_fit_opts* opts,
+                 void* stream, gv_model** out);
+
+/*
+ * gv_model_import -- build a model from given landmarks and projections
+ * (for instance from another fit).  mu: host C x D, A and B: host C x d x D,
+ * all FP64, copied.  Errors: GV_EINVAL, GV_ENONFINITE, GV_ENOMEM, GV_EDEVICE.
+ */
+gv_status gv_model_import(const double* mu, const double* A, const double* B,
+                          int32_t C, int32_t d, int32_t D, gv_model** out);
+
+/* Shape of a model. */
+gv_status gv_model_shape(const gv_model* model, int32_t* C, int32_t* d, int32_t* D);
+
+/* gv_model_export -- copy mu (C x D), A and B (C x d x D) to host FP64 arrays;
+ * any pointer may be NULL to skip it. */
+gv_status gv_model_export(const gv_model* model, double* mu, double* A, double* B);
+
+/*
+ * gv_model_stats -- fit diagnostics, host arrays, any may be NULL:
+ * KQ (D x D, the mean second moment of the learn queries), KX (C x D x D,
+ * per-cluster sums), lam_Q (D, eigenvalues of K_Q, decreasing), lam_c
+ * (C x D, eigenvalues of W K_{X_c} W, decreasing), counts (C learn vectors
+ * per cluster), fallback (C flags: pooled projection used), iters (k-means
+ * centre updates).  Imported models return GV_EUNSUPPORTED.
+ */
+gv_status gv_model_stats(const gv_model* model, double* KQ, double* KX, double* lam_Q,
+                         double* lam_c, int64_t* counts, uint8_t* fallback, int32_t* iters);
+
+void gv_model_destroy(gv_model* model);
+
+/* ------------------------------------------------------------------ encode */
+
+/*
+ * gv_encode -- index build (Section 4, Eq. 9 and Eq. 10).
+ *
+ * X       device, n x D FP32 database vectors (n >= 1).
+ * fmt     storage format of the reduced vectors.
+ * copy_X  nonzero: the index keeps its own copy of X (for the full-dimension
+ *         rerank); zero: it borrows X, which must then outlive the index and
+ *         stay unchanged.
+ *
+ * Computes tag_i = arg-max_c <x_i, mu_c> in FP64 (lowest c on ties), groups the
+ * rows by tag (stable: increasing ids inside a cluster), computes
+ * v_i = fl32(B_{tag_i} x_i) with FP64 accumulation, and per cluster a
+ * power-of-two scale s_c mapping the cluster's largest |v| into (T/2, T]
+ * (T = 448 for FP8, 65504 for FP16, 1 for BF16; s_c = 1 for FP32), then stores
+ * rnd(v / s_c), rounded to nearest even with saturation.
+ *
+ * Errors: GV_EINVAL, GV_ENOTFIT, GV_ENONFINITE, GV_ENOMEM, GV_EDEVICE.
+ * Synchronises `stream` before returning.
+ */
+gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format fmt,
+                    int32_t copy_X, void* stream, gv_index** out);
+
+/* Shape of an index: rows, clusters, reduced dim, padded row length (elements), format. */
+gv_status gv_index_shape(const gv_index* index, int64_t* n, int32_t* C, int32_t* d,
+                         int32_t* d_pad, int32_t* fmt);
+
+/*
+ * gv_index_export -- host copies of the index (any pointer may be NULL):
+ * tags (n, uint8, original order), offsets (C + 1, grouped segment starts),
+ * ids (n, int32, original id of each grouped position), xlow (n x d_pad
+ * elements of the storage format, raw bits, grouped order, zero padded),
+ * scale (C, FP32 power-of-two s_c).
+ */
+gv_status gv_index_export(const gv_index* index, uint8_t* tags, int64_t* offsets, int32_t* ids,
+                          void* xlow, float* scale);
+
+void gv_index_destroy(gv_index* index);
+
+/* ------------------------------------------------------------------ search */
+
+/*
+ * gv_search -- multi-step search (Algorithm 1) with eager views (Algorithm 4).
+ *
+ * Q           device, m x D FP32 queries (m >= 0; m == 0 is a no-op).
+ * k, kappa    1 <= k <= kappa <= min(n, 256).
+ * out_ids     device, m x k int32: original row ids of the k best rerank
+ *             scores, ordered by (exact score desc, id asc).
+ * out_scores  device, m x k FP32 (may be NULL): fl32 of the exact <q, x>
+ *             computed with FP64 accumulation.
+ *
+ * Stages, one launch sequence on `stream`:
+ *   S1  q_c = fl32(A_c q) for every cluster (FP64 accumulation), then the
+ *       per-(query, cluster) power-of-two scale t and the view
+ *       q^_c = rnd(q_c / t) in the index format (t = 1 for FP32);
+ *   S2  for every database vector i of cluster c:
+ *       s_i = s_c * t_{q,c} * <q^_c, x^_i>, FP32 accumulation on the matrix cores;
+ *   S3  the kappa best s_i per query, ordered by (s_i desc, id asc);
+ *   S4  exact <q, x_i> over the kappa candidates, top k.
+ * Scratch memory is taken from the stream-ordered allocator.
+ *
+ * Errors: GV_EINVAL, GV_ENOTFIT, GV_ENOMEM, GV_EDEVICE.
+ */
+gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q, int64_t m,
+                    int32_t k, int32_t kappa, int32_t* out_ids, float* out_scores, void* stream);
+
+/*
+ * gv_project -- stage S1 alone (Algorithm 4, preprocess).
+ * Q device m x D FP32.  qc device m x C x d_pad FP32 (may be NULL): q_c,
+ * zero padded.  t device m x C FP32: the scales.  qhat device m x C x d_pad
+ * elements of `fmt` (raw bits, zero padded).  Errors as gv_search.
+ */
+gv_status gv_project(const gv_model* model, gv_format fmt, const float* Q, int64_t m,
+                     float* qc, float* t, void* qhat, void* stream);
+
+/*
+ * gv_score_topk -- stages S2 and S3 for views produced by gv_project.
+ * qhat, t  device, as written by gv_project for this index's format.
+ * cand_ids device m x kappa int32, cand_scores device m x kappa FP32:
+ * the kappa best reduced scores per query, ordered by (score desc, id asc);
+ * ids are original row ids.  1 <= kappa <= min(n, 256).  Errors as gv_search.
+ */
+gv_status gv_score_topk(const gv_index* index, const void* qhat, const float* t, int64_t m,
+                        int32_t kappa, int32_t* cand_ids, float* cand_scores, void* stream);
+
+/*
+ * gv_rerank -- stage S4 (Algorithm 1, postprocessing).
+ * Q device m x D FP32; cand_ids device m x kappa int32 (valid original ids);
+ * out_ids device m x k int32, out_scores device m x k FP32 (may be NULL):
+ * the k best exact <q, x> (FP64 accumulation) among the candidates, ordered by
+ * (score desc, id asc).  1 <= k <= kappa <= 256.  Errors as gv_search.
+ */
+gv_status gv_rerank(const gv_index* index, const float* Q, int64_t m, const int32_t* cand_ids,
+                    int32_t kappa, int32_t k, int32_t* out_ids, float* out_scores, void* stream);
+
+/*
+ * gv_search_tuning -- override the launch shape of S2/S3 for the calling
+ * thread's following searches (0 restores the automatic choice):
+ * splits = number of database splits P, qpw = queries per wavefront (32, 64
+ * or 128).  Results do not depend on these; only speed does.
+ */
+gv_status gv_search_tuning(int32_t splits, int32_t qpw);
+
+/*
+ * gv_profile_enable / gv_profile_read -- measurement hooks for benchmarks.
+ * While enabled (on != 0), every scoring launch of S2/S3 and every merge launch
+ * is bracketed by HIP events recorded on the stream it runs on.
+ * gv_profile_read waits for the recorded events, returns the summed durations
+ * (milliseconds) and launch counts of the scoring kernel and of the merge
+ * kernels (any pointer may be NULL), and clears the record.  Off by default;
+ * enabling it costs two event records per launch.
+ */
+gv_status gv_profile_enable(int32_t on);
+gv_status gv_profile_read(double* ms_score, int64_t* n_score, double* ms_merge, int64_t* n_merge);
+
+/*
+ * gv_host_eigh -- the host FP64 symmetric eigensolver the fit uses for the
+ * eigendecompositions of Section 3.2 (Householder tridiagonalisation, then
+ * implicit QR steps with Wilkinson shifts).  A: host n x n symmetric, read
+ * only; lam: host n eigenvalues, decreasing; Vt: host n x n, row r is the unit
+ * eigenvector of lam[r].  Runs on the CPU only.  Errors: GV_EINVAL.
+ */
+gv_status gv_host_eigh(int32_t n, const double* A, double* lam, double* Vt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GLEANVEC_H */

@@ -1,0 +1,288 @@
+"""GleanVec / LeanVec-Sphering on MI355X (gfx950): Python binding.
+
+A thin ctypes layer over ``libgleanvec.so`` (C ABI in ``include/gleanvec.h``).
+It only marshals arguments: torch tensors supply device memory and the
+current HIP stream; every step of fit, encode and search runs in the
+library's HIP kernels.  Importing this package fails loudly when the library
+has not been built (``python -m paper_2410_22347_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgleanvec.so")
+
+FP32, FP16, BF16, FP8 = 0, 1, 2, 3
+FORMATS = {"fp32": FP32, "fp16": FP16, "bf16": BF16, "fp8": FP8}
+FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
+
+_STATUS = {0: "GV_OK", -1: "GV_EINVAL", -2: "GV_ENOMEM", -3: "GV_EDEVICE", -4: "GV_ENOTFIT",
+           -5: "GV_ENONFINITE", -6: "GV_EUNSUPPORTED"}
+
+EXPORTED = [
+    "gv_status_string", "gv_last_error", "gv_fit", "gv_model_import", "gv_model_shape",
+    "gv_model_export", "gv_model_stats", "gv_model_destroy", "gv_encode", "gv_index_shape",
+    "gv_index_export", "gv_index_destroy", "gv_search", "gv_project", "gv_score_topk",
+    "gv_rerank", "gv_search_tuning", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
+]
+
+
+class GleanVecError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2410_22347_amd/build.py`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+
+
+class _FitOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("kmeans_sample", ctypes.c_int64), ("init_centroids", _vp)]
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_sig("gv_status_string", [ctypes.c_int], ctypes.c_char_p)
+_sig("gv_last_error", [], ctypes.c_char_p)
+_sig("gv_fit", [_vp, _i64, _vp, _i64, _i32, _i32, _i32, _u64, ctypes.POINTER(_FitOpts), _vp, ctypes.POINTER(_vp)])
+_sig("gv_model_import", [_vp, _vp, _vp, _i32, _i32, _i32, ctypes.POINTER(_vp)])
+_sig("gv_model_shape", [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+_sig("gv_model_export", [_vp, _vp, _vp, _vp])
+_sig("gv_model_stats", [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32)])
+_sig("gv_model_destroy", [_vp], None)
+_sig("gv_encode", [_vp, _vp, _i64, ctypes.c_int, _i32, _vp, ctypes.POINTER(_vp)])
+_sig("gv_index_shape", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                        ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+_sig("gv_index_export", [_vp, _vp, _vp, _vp, _vp, _vp])
+_sig("gv_index_destroy", [_vp], None)
+_sig("gv_search", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
+_sig("gv_project", [_vp, ctypes.c_int, _vp, _i64, _vp, _vp, _vp, _vp])
+_sig("gv_score_topk", [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp])
+_sig("gv_rerank", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
+_sig("gv_search_tuning", [_i32, _i32])
+_sig("gv_host_eigh", [_i32, _vp, _vp, _vp])
+_sig("gv_profile_enable", [_i32])
+_sig("gv_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(_i64)])
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise GleanVecError(status, where, (_lib.gv_last_error() or b"").decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f32(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.dim() == 2):
+        raise ValueError("expected a contiguous 2-D float32 CUDA tensor")
+    return t
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Model:
+    """Landmarks mu_c and projections A_c, B_c (owned by the library)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        C, d, D = _i32(), _i32(), _i32()
+        _check(_lib.gv_model_shape(self._h, ctypes.byref(C), ctypes.byref(d), ctypes.byref(D)), "gv_model_shape")
+        self.C, self.d, self.D = C.value, d.value, D.value
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.gv_model_destroy(self._h)
+            self._h = None
+
+    def export(self):
+        mu = np.empty((self.C, self.D))
+        A = np.empty((self.C, self.d, self.D))
+        B = np.empty((self.C, self.d, self.D))
+        _check(_lib.gv_model_export(self._h, _np_ptr(mu), _np_ptr(A), _np_ptr(B)), "gv_model_export")
+        return mu, A, B
+
+    def stats(self):
+        C, D = self.C, self.D
+        KQ = np.empty((D, D)); KX = np.empty((C, D, D)); lamQ = np.empty(D); lamc = np.empty((C, D))
+        counts = np.empty(C, np.int64); fb = np.empty(C, np.uint8); it = _i32()
+        _check(_lib.gv_model_stats(self._h, _np_ptr(KQ), _np_ptr(KX), _np_ptr(lamQ), _np_ptr(lamc),
+                                   _np_ptr(counts), _np_ptr(fb), ctypes.byref(it)), "gv_model_stats")
+        return dict(KQ=KQ, KX=KX, lam_Q=lamQ, lam_c=lamc, counts=counts, fallback=fb.astype(bool),
+                    iters=it.value)
+
+
+class Index:
+    """Grouped, quantised reduced database plus the FP32 vectors for the rerank."""
+
+    def __init__(self, handle, keep=None):
+        self._h = handle
+        self._keep = keep          # a borrowed X must outlive the index
+        n, C, d, dp, f = _i64(), _i32(), _i32(), _i32(), _i32()
+        _check(_lib.gv_index_shape(self._h, ctypes.byref(n), ctypes.byref(C), ctypes.byref(d), ctypes.byref(dp),
+                                   ctypes.byref(f)), "gv_index_shape")
+        self.n, self.C, self.d, self.d_pad, self.fmt = n.value, C.value, d.value, dp.value, f.value
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.gv_index_destroy(self._h)
+            self._h = None
+
+    def export(self):
+        eb = {FP32: 4, FP16: 2, BF16: 2, FP8: 1}[self.fmt]
+        dt = {4: np.uint32, 2: np.uint16, 1: np.uint8}[eb]
+        tags = np.empty(self.n, np.uint8)
+        off = np.empty(self.C + 1, np.int64)
+        ids = np.empty(self.n, np.int32)
+        xlow = np.empty((self.n, self.d_pad), dt)
+        scale = np.empty(self.C, np.float32)
+        _check(_lib.gv_index_export(self._h, _np_ptr(tags), _np_ptr(off), _np_ptr(ids), _np_ptr(xlow),
+                                    _np_ptr(scale)), "gv_index_export")
+        return dict(tags=tags, offsets=off, ids=ids, xlow=xlow, scale=scale)
+
+
+def fit(X_learn, Q_learn, d: int, C: int, seed: int, max_iter: int = 0, kmeans_sample: int = 0,
+        init_centroids=None) -> Model:
+    """GleanVec learning (Algorithm 5) on the current device."""
+    _dev_f32(X_learn); _dev_f32(Q_learn)
+    opts = _FitOpts(max_iter, kmeans_sample, None)
+    keep = None
+    if init_centroids is not None:
+        keep = np.ascontiguousarray(init_centroids, np.float64)
+        opts.init_centroids = keep.ctypes.data
+    h = _vp()
+    _check(_lib.gv_fit(_ptr(X_learn), X_learn.shape[0], _ptr(Q_learn), Q_learn.shape[0], X_learn.shape[1], d, C,
+                       seed & ((1 << 64) - 1), ctypes.byref(opts), _stream(), ctypes.byref(h)), "gv_fit")
+    return Model(h)
+
+
+def model_import(mu, A, B) -> Model:
+    mu = np.ascontiguousarray(mu, np.float64)
+    A = np.ascontiguousarray(A, np.float64)
+    B = np.ascontiguousarray(B, np.float64)
+    C, d, D = A.shape
+    h = _vp()
+    _check(_lib.gv_model_import(_np_ptr(mu), _np_ptr(A), _np_ptr(B), C, d, D, ctypes.byref(h)), "gv_model_import")
+    return Model(h)
+
+
+def encode(model: Model, X, fmt, copy_X: bool = False) -> Index:
+    _dev_f32(X)
+    f = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+    h = _vp()
+    _check(_lib.gv_encode(model._h, _ptr(X), X.shape[0], f, 1 if copy_X else 0, _stream(), ctypes.byref(h)),
+           "gv_encode")
+    return Index(h, keep=None if copy_X else X)
+
+
+def search(model: Model, index: Index, Q, k: int, kappa: int, with_scores: bool = True):
+    """Multi-step search; returns (ids [m, k] int32, scores [m, k] float32 or None)."""
+    import torch
+    _dev_f32(Q)
+    m = Q.shape[0]
+    ids = torch.empty((m, k), dtype=torch.int32, device=Q.device)
+    sc = torch.empty((m, k), dtype=torch.float32, device=Q.device) if with_scores else None
+    _check(_lib.gv_search(model._h, index._h, _ptr(Q), m, k, kappa, _ptr(ids), _ptr(sc), _stream()), "gv_search")
+    return ids, sc
+
+
+def _elem_dtype(fmt):
+    import torch
+    return {FP32: torch.float32, FP16: torch.int16, BF16: torch.int16, FP8: torch.uint8}[fmt]
+
+
+def project(model: Model, fmt, Q, want_qc: bool = True):
+    """Stage S1: returns (q_c [m, C, d_pad] f32 or None, t [m, C] f32, qhat [m, C, d_pad] raw format)."""
+    import torch
+    _dev_f32(Q)
+    f = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+    m = Q.shape[0]
+    dp = (model.d + 15) // 16 * 16
+    qc = torch.empty((m, model.C, dp), dtype=torch.float32, device=Q.device) if want_qc else None
+    t = torch.empty((m, model.C), dtype=torch.float32, device=Q.device)
+    qhat = torch.empty((m, model.C, dp), dtype=_elem_dtype(f), device=Q.device)
+    _check(_lib.gv_project(model._h, f, _ptr(Q), m, _ptr(qc), _ptr(t), _ptr(qhat), _stream()), "gv_project")
+    return qc, t, qhat
+
+
+def score_topk(index: Index, qhat, t, kappa: int):
+    """Stages S2 + S3: returns (cand_ids [m, kappa] int32, cand_scores [m, kappa] f32)."""
+    import torch
+    m = t.shape[0]
+    ids = torch.empty((m, kappa), dtype=torch.int32, device=t.device)
+    sc = torch.empty((m, kappa), dtype=torch.float32, device=t.device)
+    _check(_lib.gv_score_topk(index._h, _ptr(qhat), _ptr(t), m, kappa, _ptr(ids), _ptr(sc), _stream()),
+           "gv_score_topk")
+    return ids, sc
+
+
+def rerank(index: Index, Q, cand_ids, k: int):
+    """Stage S4: returns (ids [m, k] int32, scores [m, k] f32)."""
+    import torch
+    _dev_f32(Q)
+    m, kappa = cand_ids.shape
+    ids = torch.empty((m, k), dtype=torch.int32, device=Q.device)
+    sc = torch.empty((m, k), dtype=torch.float32, device=Q.device)
+    _check(_lib.gv_rerank(index._h, _ptr(Q), m, _ptr(cand_ids), kappa, k, _ptr(ids), _ptr(sc), _stream()),
+           "gv_rerank")
+    return ids, sc
+
+
+def search_tuning(splits: int = 0, qpw: int = 0):
+    _check(_lib.gv_search_tuning(splits, qpw), "gv_search_tuning")
+
+
+def host_eigh(A):
+    """The library's host FP64 symmetric eigensolver (decreasing eigenvalues, rows = vectors)."""
+    A = np.ascontiguousarray(A, np.float64)
+    n = A.shape[0]
+    lam = np.empty(n)
+    Vt = np.empty((n, n))
+    _check(_lib.gv_host_eigh(n, _np_ptr(A), _np_ptr(lam), _np_ptr(Vt)), "gv_host_eigh")
+    return lam, Vt
+
+
+def profile_enable(on: bool = True):
+    _check(_lib.gv_profile_enable(1 if on else 0), "gv_profile_enable")
+
+
+def profile_read():
+    """(ms_score, n_score, ms_merge, n_merge) since the last read; waits for the events."""
+    a, c = ctypes.c_double(), ctypes.c_double()
+    b, d = _i64(), _i64()
+    _check(_lib.gv_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
+           "gv_profile_read")
+    return a.value, b.value, c.value, d.value
+
+
+def status_string(code: int) -> str:
+    return _lib.gv_status_string(code).decode()

@@ -1,0 +1,463 @@
+// C ABI of the library: argument validation, handle lifetime and the
+// sequencing of the device stages.  No exception crosses this boundary.
+#include <cstring>
+#include <exception>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "common.hpp"
+
+namespace gv {
+
+static thread_local std::string g_err;
+static thread_local int g_splits = 0, g_qpw = 0;
+void set_error(const std::string& msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+int tuned_splits() { return g_splits; }
+int tuned_qpw() { return g_qpw; }
+
+namespace {
+struct ProfRec {
+  hipEvent_t a, b;
+  int kind;
+};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof;
+hipEvent_t g_prof_open[2] = {nullptr, nullptr};
+bool g_prof_on = false;
+}  // namespace
+
+bool profiling() { return g_prof_on; }
+
+void profile_mark(hipStream_t st, int kind, bool begin) {
+  if (!g_prof_on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, st);
+  if (begin) {
+    if (g_prof_open[kind]) (void)hipEventDestroy(g_prof_open[kind]);
+    g_prof_open[kind] = e;
+  } else if (g_prof_open[kind]) {
+    g_prof.push_back({g_prof_open[kind], e, kind});
+    g_prof_open[kind] = nullptr;
+  } else {
+    (void)hipEventDestroy(e);
+  }
+}
+
+namespace {
+
+__global__ void k_nonfinite_f32(const float* __restrict__ p, int64_t count, int* __restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(p[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+bool finite_host(const double* p, size_t count) {
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+template <typename F>
+gv_status guarded(F f) {
+  try {
+    clear_error();
+    return f();
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GV_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return GV_EDEVICE;
+  } catch (...) {
+    set_error("unknown failure");
+    return GV_EDEVICE;
+  }
+}
+
+bool valid(const gv_model* m) { return m && m->magic == kModelMagic; }
+bool valid(const gv_index* x) { return x && x->magic == kIndexMagic; }
+
+gv_status alloc_model(int C, int d, int D, gv_model** out) {
+  gv_model* m = new gv_model();
+  m->magic = kModelMagic;
+  m->C = C;
+  m->d = d;
+  m->D = D;
+  m->mu = m->A = m->B = nullptr;
+  m->fitted = false;
+  m->iters = 0;
+  if (hipGetDevice(&m->device) != hipSuccess) m->device = 0;
+  hipError_t e1 = hipMalloc(&m->mu, sizeof(double) * C * D);
+  hipError_t e2 = hipMalloc(&m->A, sizeof(double) * C * d * D);
+  hipError_t e3 = hipMalloc(&m->B, sizeof(double) * C * d * D);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+    gv_model_destroy(m);
+    set_error("device allocation of the model failed");
+    return GV_ENOMEM;
+  }
+  *out = m;
+  return GV_OK;
+}
+
+}  // namespace
+
+gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite) {
+  int* flag = nullptr;
+  GV_HIP(hipMallocAsync((void**)&flag, sizeof(int), st));
+  GV_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  if (count > 0) {
+    int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_nonfinite_f32, dim3((unsigned)blocks), dim3(256), 0, st, p, count, flag);
+    GV_HIP(hipGetLastError());
+  }
+  int h = 0;
+  GV_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  GV_HIP(hipFreeAsync(flag, st));
+  GV_HIP(hipStreamSynchronize(st));
+  *finite = (h == 0);
+  return GV_OK;
+}
+
+}  // namespace gv
+
+using namespace gv;
+
+extern "C" {
+
+const char* gv_status_string(gv_status s) {
+  switch (s) {
+    case GV_OK: return "ok";
+    case GV_EINVAL: return "invalid argument";
+    case GV_ENOMEM: return "out of memory";
+    case GV_EDEVICE: return "device error";
+    case GV_ENOTFIT: return "invalid or missing handle";
+    case GV_ENONFINITE: return "non-finite input";
+    case GV_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* gv_last_error(void) { return g_err.c_str(); }
+
+gv_status gv_fit(const float* X_learn, int64_t n_learn, const float* Q_learn, int64_t m_learn, int32_t D, int32_t d,
+                 int32_t C, uint64_t seed, const gv_fit_opts* opts, void* stream, gv_model** out) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(out != nullptr, "gv_fit: out is NULL");
+    *out = nullptr;
+    GV_REQUIRE(X_learn && Q_learn, "gv_fit: NULL input");
+    GV_REQUIRE(D >= 1 && d >= 1 && d <= D, "gv_fit: need 1 <= d <= D");
+    GV_REQUIRE(C >= 1 && C <= 255, "gv_fit: need 1 <= C <= 255");
+    GV_REQUIRE(n_learn >= C && m_learn >= 1, "gv_fit: need n_learn >= C and m_learn >= 1");
+    GV_REQUIRE(n_learn <= 0x7fffffffLL, "gv_fit: n_learn too large");
+    if (opts && opts->init_centroids) {
+      if (!finite_host(opts->init_centroids, (size_t)C * D)) return GV_ENONFINITE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    bool f1 = false, f2 = false;
+    GV_TRY(check_finite_f32(X_learn, n_learn * D, st, &f1));
+    GV_TRY(check_finite_f32(Q_learn, m_learn * D, st, &f2));
+    if (!f1 || !f2) {
+      set_error("gv_fit: NaN or Inf in the learn data");
+      return GV_ENONFINITE;
+    }
+    gv_model* m = nullptr;
+    GV_TRY(alloc_model(C, d, D, &m));
+    gv_status s = fit_impl(X_learn, n_learn, Q_learn, m_learn, D, d, C, seed, opts, st, m);
+    if (s != GV_OK) {
+      gv_model_destroy(m);
+      return s;
+    }
+    *out = m;
+    return GV_OK;
+  });
+}
+
+gv_status gv_model_import(const double* mu, const double* A, const double* B, int32_t C, int32_t d, int32_t D,
+                          gv_model** out) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(out != nullptr, "gv_model_import: out is NULL");
+    *out = nullptr;
+    GV_REQUIRE(mu && A && B, "gv_model_import: NULL input");
+    GV_REQUIRE(D >= 1 && d >= 1 && d <= D && C >= 1 && C <= 255, "gv_model_import: bad shape");
+    if (!finite_host(mu, (size_t)C * D) || !finite_host(A, (size_t)C * d * D) || !finite_host(B, (size_t)C * d * D))
+      return GV_ENONFINITE;
+    gv_model* m = nullptr;
+    GV_TRY(alloc_model(C, d, D, &m));
+    hipError_t e = hipMemcpy(m->mu, mu, sizeof(double) * C * D, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->A, A, sizeof(double) * C * d * D, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->B, B, sizeof(double) * C * d * D, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      gv_model_destroy(m);
+      set_error(std::string("gv_model_import: ") + hipGetErrorString(e));
+      return GV_EDEVICE;
+    }
+    *out = m;
+    return GV_OK;
+  });
+}
+
+gv_status gv_model_shape(const gv_model* m, int32_t* C, int32_t* d, int32_t* D) {
+  if (!valid(m)) return GV_ENOTFIT;
+  if (C) *C = m->C;
+  if (d) *d = m->d;
+  if (D) *D = m->D;
+  return GV_OK;
+}
+
+gv_status gv_model_export(const gv_model* m, double* mu, double* A, double* B) {
+  return guarded([&]() -> gv_status {
+    if (!valid(m)) return GV_ENOTFIT;
+    const size_t cdD = (size_t)m->C * m->d * m->D;
+    if (mu) GV_HIP(hipMemcpy(mu, m->mu, sizeof(double) * m->C * m->D, hipMemcpyDeviceToHost));
+    if (A) GV_HIP(hipMemcpy(A, m->A, sizeof(double) * cdD, hipMemcpyDeviceToHost));
+    if (B) GV_HIP(hipMemcpy(B, m->B, sizeof(double) * cdD, hipMemcpyDeviceToHost));
+    return GV_OK;
+  });
+}
+
+gv_status gv_model_stats(const gv_model* m, double* KQ, double* KX, double* lam_Q, double* lam_c, int64_t* counts,
+                         uint8_t* fallback, int32_t* iters) {
+  if (!valid(m)) return GV_ENOTFIT;
+  if (!m->fitted) return GV_EUNSUPPORTED;
+  if (KQ) std::memcpy(KQ, m->KQ.data(), sizeof(double) * m->KQ.size());
+  if (KX) std::memcpy(KX, m->KX.data(), sizeof(double) * m->KX.size());
+  if (lam_Q) std::memcpy(lam_Q, m->lamQ.data(), sizeof(double) * m->lamQ.size());
+  if (lam_c) std::memcpy(lam_c, m->lamc.data(), sizeof(double) * m->lamc.size());
+  if (counts) std::memcpy(counts, m->counts.data(), sizeof(int64_t) * m->counts.size());
+  if (fallback) std::memcpy(fallback, m->fallback.data(), m->fallback.size());
+  if (iters) *iters = m->iters;
+  return GV_OK;
+}
+
+void gv_model_destroy(gv_model* m) {
+  if (!m || m->magic != kModelMagic) return;
+  m->magic = 0;
+  if (m->mu) (void)hipFree(m->mu);
+  if (m->A) (void)hipFree(m->A);
+  if (m->B) (void)hipFree(m->B);
+  delete m;
+}
+
+gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format fmt, int32_t copy_X, void* stream,
+                    gv_index** out) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(out != nullptr, "gv_encode: out is NULL");
+    *out = nullptr;
+    if (!valid(model)) return GV_ENOTFIT;
+    GV_REQUIRE(X != nullptr, "gv_encode: X is NULL");
+    GV_REQUIRE(n >= 1 && n <= 0x7fffffffLL, "gv_encode: need 1 <= n < 2^31");
+    GV_REQUIRE(fmt >= GV_FP32 && fmt <= GV_FP8_E4M3, "gv_encode: unknown format");
+    GV_REQUIRE(model->d <= 256, "gv_encode: reduced dimension above 256 is not supported");
+    hipStream_t st = (hipStream_t)stream;
+    bool fin = false;
+    GV_TRY(check_finite_f32(X, n * model->D, st, &fin));
+    if (!fin) {
+      set_error("gv_encode: NaN or Inf in X");
+      return GV_ENONFINITE;
+    }
+    int dev = 0;
+    GV_HIP(hipGetDevice(&dev));
+    gv_index* x = new gv_index();
+    x->device = dev;
+    x->magic = kIndexMagic;
+    x->C = model->C;
+    x->d = model->d;
+    x->dp = pad16(model->d);
+    x->D = model->D;
+    x->fmt = fmt;
+    x->n = n;
+    x->tags = nullptr;
+    x->offsets = nullptr;
+    x->ids = nullptr;
+    x->xlow = nullptr;
+    x->scale = nullptr;
+    x->X = nullptr;
+    x->own_X = copy_X != 0;
+    auto fail = [&](gv_status s) {
+      gv_index_destroy(x);
+      return s;
+    };
+    if (hipMalloc(&x->tags, n) != hipSuccess || hipMalloc(&x->offsets, sizeof(int64_t) * (x->C + 1)) != hipSuccess ||
+        hipMalloc(&x->ids, sizeof(int32_t) * n) != hipSuccess ||
+        hipMalloc(&x->xlow, (size_t)n * x->dp * fmt_bytes(fmt)) != hipSuccess ||
+        hipMalloc(&x->scale, sizeof(float) * x->C) != hipSuccess) {
+      set_error("gv_encode: device allocation failed");
+      return fail(GV_ENOMEM);
+    }
+    if (x->own_X) {
+      float* copy = nullptr;
+      if (hipMalloc(&copy, sizeof(float) * n * x->D) != hipSuccess) {
+        set_error("gv_encode: device allocation of the X copy failed");
+        return fail(GV_ENOMEM);
+      }
+      x->X = copy;
+      if (hipMemcpyAsync(copy, X, sizeof(float) * n * x->D, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(GV_EDEVICE);
+    } else {
+      x->X = X;
+    }
+    gv_status s = encode_impl(model, X, n, fmt, st, x);
+    if (s != GV_OK) return fail(s);
+    *out = x;
+    return GV_OK;
+  });
+}
+
+gv_status gv_index_shape(const gv_index* x, int64_t* n, int32_t* C, int32_t* d, int32_t* d_pad, int32_t* fmt) {
+  if (!valid(x)) return GV_ENOTFIT;
+  if (n) *n = x->n;
+  if (C) *C = x->C;
+  if (d) *d = x->d;
+  if (d_pad) *d_pad = x->dp;
+  if (fmt) *fmt = x->fmt;
+  return GV_OK;
+}
+
+gv_status gv_index_export(const gv_index* x, uint8_t* tags, int64_t* offsets, int32_t* ids, void* xlow, float* scale) {
+  return guarded([&]() -> gv_status {
+    if (!valid(x)) return GV_ENOTFIT;
+    if (tags) GV_HIP(hipMemcpy(tags, x->tags, x->n, hipMemcpyDeviceToHost));
+    if (offsets) std::memcpy(offsets, x->h_offsets.data(), sizeof(int64_t) * (x->C + 1));
+    if (ids) GV_HIP(hipMemcpy(ids, x->ids, sizeof(int32_t) * x->n, hipMemcpyDeviceToHost));
+    if (xlow) GV_HIP(hipMemcpy(xlow, x->xlow, (size_t)x->n * x->dp * fmt_bytes(x->fmt), hipMemcpyDeviceToHost));
+    if (scale) GV_HIP(hipMemcpy(scale, x->scale, sizeof(float) * x->C, hipMemcpyDeviceToHost));
+    return GV_OK;
+  });
+}
+
+void gv_index_destroy(gv_index* x) {
+  if (!x || x->magic != kIndexMagic) return;
+  x->magic = 0;
+  if (x->tags) (void)hipFree(x->tags);
+  if (x->offsets) (void)hipFree(x->offsets);
+  if (x->ids) (void)hipFree(x->ids);
+  if (x->xlow) (void)hipFree(x->xlow);
+  if (x->scale) (void)hipFree(x->scale);
+  if (x->own_X && x->X) (void)hipFree((void*)x->X);
+  delete x;
+}
+
+static gv_status check_search_args(const gv_index* idx, int64_t m, int32_t k, int32_t kappa) {
+  GV_REQUIRE(m >= 0, "search: m < 0");
+  GV_REQUIRE(kappa >= 1 && kappa <= 256, "search: need 1 <= kappa <= 256");
+  GV_REQUIRE(k >= 1 && k <= kappa, "search: need 1 <= k <= kappa");
+  GV_REQUIRE(kappa <= idx->n, "search: need kappa <= n");
+  return GV_OK;
+}
+
+gv_status gv_project(const gv_model* model, gv_format fmt, const float* Q, int64_t m, float* qc, float* t, void* qhat,
+                     void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(model)) return GV_ENOTFIT;
+    GV_REQUIRE(m >= 0, "gv_project: m < 0");
+    GV_REQUIRE(fmt >= GV_FP32 && fmt <= GV_FP8_E4M3, "gv_project: unknown format");
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(Q && t && qhat, "gv_project: NULL argument");
+    return project_impl(model, fmt, Q, m, qc, t, qhat, (hipStream_t)stream);
+  });
+}
+
+gv_status gv_score_topk(const gv_index* index, const void* qhat, const float* t, int64_t m, int32_t kappa,
+                        int32_t* cand_ids, float* cand_scores, void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(index)) return GV_ENOTFIT;
+    GV_TRY(check_search_args(index, m, 1, kappa));
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(qhat && t && cand_ids && cand_scores, "gv_score_topk: NULL argument");
+    return score_topk_impl(index, qhat, t, m, kappa, cand_ids, cand_scores, (hipStream_t)stream);
+  });
+}
+
+gv_status gv_rerank(const gv_index* index, const float* Q, int64_t m, const int32_t* cand_ids, int32_t kappa, int32_t k,
+                    int32_t* out_ids, float* out_scores, void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(index)) return GV_ENOTFIT;
+    GV_TRY(check_search_args(index, m, k, kappa));
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(Q && cand_ids && out_ids, "gv_rerank: NULL argument");
+    return rerank_impl(index, Q, m, cand_ids, kappa, k, out_ids, out_scores, (hipStream_t)stream);
+  });
+}
+
+gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int32_t k, int32_t kappa,
+                    int32_t* out_ids, float* out_scores, void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(model) || !valid(index)) return GV_ENOTFIT;
+    GV_REQUIRE(model->C == index->C && model->d == index->d && model->D == index->D,
+               "gv_search: model and index shapes differ");
+    GV_TRY(check_search_args(index, m, k, kappa));
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(Q && out_ids, "gv_search: NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int C = index->C, dp = index->dp;
+    const size_t eb = fmt_bytes(index->fmt);
+    float* t = nullptr;
+    void* qhat = nullptr;
+    int32_t* cand = nullptr;
+    float* cand_sc = nullptr;
+    GV_HIP(hipMallocAsync((void**)&t, sizeof(float) * m * C, st));
+    GV_HIP(hipMallocAsync(&qhat, eb * m * C * dp, st));
+    GV_HIP(hipMallocAsync((void**)&cand, sizeof(int32_t) * m * kappa, st));
+    GV_HIP(hipMallocAsync((void**)&cand_sc, sizeof(float) * m * kappa, st));
+    gv_status s = project_impl(model, index->fmt, Q, m, nullptr, t, qhat, st);
+    if (s == GV_OK) s = score_topk_impl(index, qhat, t, m, kappa, cand, cand_sc, st);
+    if (s == GV_OK) s = rerank_impl(index, Q, m, cand, kappa, k, out_ids, out_scores, st);
+    (void)hipFreeAsync(t, st);
+    (void)hipFreeAsync(qhat, st);
+    (void)hipFreeAsync(cand, st);
+    (void)hipFreeAsync(cand_sc, st);
+    return s;
+  });
+}
+
+gv_status gv_search_tuning(int32_t splits, int32_t qpw) {
+  if (splits < 0 || splits > 4096) return GV_EINVAL;
+  if (qpw != 0 && qpw != 32 && qpw != 64 && qpw != 128) return GV_EINVAL;
+  g_splits = splits;
+  g_qpw = qpw;
+  return GV_OK;
+}
+
+gv_status gv_profile_enable(int32_t on) {
+  g_prof_on = on != 0;
+  return GV_OK;
+}
+
+gv_status gv_profile_read(double* ms_score, int64_t* n_score, double* ms_merge, int64_t* n_merge) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double ms[2] = {0.0, 0.0};
+  int64_t cnt[2] = {0, 0};
+  gv_status st = GV_OK;
+  for (auto& r : g_prof) {
+    float t = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) st = GV_EDEVICE;
+    ms[r.kind] += t;
+    cnt[r.kind] += 1;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  if (ms_score) *ms_score = ms[0];
+  if (n_score) *n_score = cnt[0];
+  if (ms_merge) *ms_merge = ms[1];
+  if (n_merge) *n_merge = cnt[1];
+  return st;
+}
+
+gv_status gv_host_eigh(int32_t n, const double* A, double* lam, double* Vt) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(n >= 1 && A && lam && Vt, "gv_host_eigh: bad arguments");
+    std::vector<double> a(A, A + (size_t)n * n), l, v;
+    eigh_desc(n, a, l, v);
+    std::memcpy(lam, l.data(), sizeof(double) * n);
+    std::memcpy(Vt, v.data(), sizeof(double) * (size_t)n * n);
+    return GV_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Shared declarations of the gfx950 GleanVec library: handles, error plumbing,
+// storage-format conversion and the 64-bit ordering key of the top-k stages.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gleanvec.h"
+
+namespace gv {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+void clear_error();
+
+#define GV_HIP(...)                                                        \
+  do {                                                                     \
+    hipError_t _e = (__VA_ARGS__);                                         \
+    if (_e != hipSuccess) {                                                \
+      ::gv::set_error(std::string(#__VA_ARGS__) + ": " + hipGetErrorString(_e)); \
+      return _e == hipErrorOutOfMemory ? GV_ENOMEM : GV_EDEVICE;           \
+    }                                                                      \
+  } while (0)
+
+#define GV_TRY(...)                     \
+  do {                                  \
+    gv_status _s = (__VA_ARGS__);       \
+    if (_s != GV_OK) return _s;         \
+  } while (0)
+
+#define GV_REQUIRE(cond, msg)           \
+  do {                                  \
+    if (!(cond)) {                      \
+      ::gv::set_error(msg);             \
+      return GV_EINVAL;                 \
+    }                                   \
+  } while (0)
+
+// ---------------------------------------------------------------- formats
+inline int fmt_bytes(int f) { return f == GV_FP32 ? 4 : (f == GV_FP8_E4M3 ? 1 : 2); }
+// reduced rows are padded with zeros to a multiple of 16 elements
+inline int pad16(int d) { return (d + 15) / 16 * 16; }
+
+// Scale targets: the block's largest magnitude is mapped into (T/2, T].
+inline double scale_target(int f) {
+  switch (f) {
+    case GV_FP16: return 65504.0;
+    case GV_BF16: return 1.0;
+    case GV_FP8_E4M3: return 448.0;
+    default: return 0.0;  // FP32: no scaling
+  }
+}
+
+// Power-of-two s with amax/s in (T/2, T] (1 for amax == 0 or T == 0), found by
+// exact comparisons against T * 2^e.
+__host__ __device__ inline float pow2_scale(float amax, double T) {
+  if (!(amax > 0.0f) || T == 0.0) return 1.0f;
+  double a = (double)amax;
+  int e = 0;
+  // coarse start from the binary exponents, then exact correction
+  int ea = 0, et = 0;
+  (void)frexp(a, &ea);
+  (void)frexp(T, &et);
+  e = ea - et;
+  while (a > ldexp(T, e)) ++e;
+  while (a <= ldexp(T, e - 1)) --e;
+  return (float)ldexp(1.0, e);
+}
+
+// Round a float64 value to the nearest value of a small binary format
+// (E exponent bits, M fraction bits, given bias), ties to even, saturating at
+// max_code; returns the bit pattern.  The value is scaled by an exact power of
+// two so rint() (round-half-even) gives the correctly rounded significand.
+template <int E, int M>
+__host__ __device__ inline uint32_t round_bits(double y, int bias, double vmax, uint32_t max_code) {
+  uint32_t sign = signbit(y) ? 1u : 0u;
+  double a = fabs(y);
+  uint32_t code;
+  if (a == 0.0) {
+    code = 0;
+  } else {
+    const int emin = 1 - bias;
+    int e = ilogb(a);
+    if (e < emin) e = emin;
+    double r = rint(ldexp(a, M - e));          // significand in units of 2^(e-M)
+    if (r >= ldexp(1.0, M + 1)) {              // carried into the next binade
+      r = ldexp(1.0, M);
+      e += 1;
+    }
+    if (ldexp(r, e - M) > vmax) {
+      code = max_code;
+    } else if (r < ldexp(1.0, M)) {            // subnormal (only possible at e == emin)
+      code = (uint32_t)r;
+    } else {
+      code = ((uint32_t)(e + bias) << M) | ((uint32_t)r - (1u << M));
+    }
+  }
+  return (sign << (E + M)) | code;
+}
+
+__host__ __device__ inline uint16_t to_fp16(double y) {
+  return (uint16_t)round_bits<5, 10>(y, 15, 65504.0, 0x7BFFu);
+}
+__host__ __device__ inline uint16_t to_bf16(double y) {
+  return (uint16_t)round_bits<8, 7>(y, 127, 3.3895313892515355e38, 0x7F7Fu);
+}
+__host__ __device__ inline uint8_t to_fp8(double y) {
+  return (uint8_t)round_bits<4, 3>(y, 7, 448.0, 0x7Eu);
+}
+
+// ---------------------------------------------------------------- ordering key
+// 64-bit key ordering candidates by (score desc, id asc): larger key = better.
+__host__ __device__ inline uint32_t order_f32(float s) {
+  s = s + 0.0f;  // -0 -> +0
+  uint32_t u;
+  memcpy(&u, &s, 4);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float unorder_f32(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+  float s;
+  memcpy(&s, &u, 4);
+  return s;
+}
+__host__ __device__ inline uint64_t make_key(float s, uint32_t id) {
+  return ((uint64_t)order_f32(s) << 32) | (uint64_t)(0xFFFFFFFFu - id);
+}
+__host__ __device__ inline float key_score(uint64_t k) { return unorder_f32((uint32_t)(k >> 32)); }
+__host__ __device__ inline uint32_t key_id(uint64_t k) { return 0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFu); }
+
+}  // namespace gv
+
+// ---------------------------------------------------------------- handles
+struct gv_model {
+  uint64_t magic;
+  int C, d, D;
+  int device;
+  double* mu;  // device C x D
+  double* A;   // device C*d x D (A_c stacked)
+  double* B;   // device C*d x D
+  bool fitted;
+  std::vector<double> KQ, KX, lamQ, lamc;
+  std::vector<int64_t> counts;
+  std::vector<uint8_t> fallback;
+  int iters;
+};
+
+struct gv_index {
+  uint64_t magic;
+  int C, d, dp, D, fmt;
+  int64_t n;
+  int device;
+  uint8_t* tags;     // device n
+  int64_t* offsets;  // device C+1
+  int32_t* ids;      // device n
+  void* xlow;        // device n x dp elements of fmt
+  float* scale;      // device C
+  const float* X;    // device n x D (owned if own_X)
+  bool own_X;
+  std::vector<int64_t> h_offsets;
+};
+
+constexpr uint64_t kModelMagic = 0x474C45414E4D4F44ull;  // "GLEANMOD"
+constexpr uint64_t kIndexMagic = 0x474C45414E494458ull;  // "GLEANIDX"
+
+namespace gv {
+// internal entry points shared between translation units
+gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, int d, int C,
+                   uint64_t seed, const gv_fit_opts* opts, hipStream_t st, gv_model* model);
+gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt, hipStream_t st,
+                      gv_index* index);
+gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m, float* qc,
+                       float* t, void* qhat, hipStream_t st);
+gv_status score_topk_impl(const gv_index* index, const void* qhat, const float* t, int64_t m,
+                          int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st);
+gv_status rerank_impl(const gv_index* index, const float* Q, int64_t m, const int32_t* cand,
+                      int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
+gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite);
+
+// FP64 matrix-core GEMM: C(i, j) = sum_k a(i, k) b(j, k) with operand layouts
+// described by GemmOperand; epilogue selects how C is stored.
+enum class Layout { RowMajor, KMajor };
+template <typename T>
+struct GemmOperand {
+  const T* p;
+  int64_t ld;
+  const int64_t* gather;  // optional: RowMajor -> row index of i; KMajor -> row index of k
+  Layout layout;
+};
+enum class Epi { StoreF64, AddF64, StoreF32Proj, StoreF32 };
+struct GemmOut {
+  void* p;
+  int64_t ldc;
+  int cd;     // StoreF32Proj: columns per cluster (d)
+  int cdp;    // StoreF32Proj: padded columns per cluster
+  const int64_t* row_map;  // StoreF32: output row of i (optional)
+};
+template <typename TA, typename TB>
+gv_status gemm_f64(int64_t M, int64_t N, int64_t K, GemmOperand<TA> a, GemmOperand<TB> b, Epi epi,
+                   GemmOut out, hipStream_t st);
+
+// host symmetric eigensolver (Householder tridiagonalisation + implicit QL/QR)
+// A: n x n symmetric (row-major, overwritten); lam: n eigenvalues decreasing;
+// Vt: n x n, row r = unit eigenvector of lam[r].
+void eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Vt);
+
+int tuned_splits();
+int tuned_qpw();
+
+// benchmark hooks: events around scoring (kind 0) and merge (kind 1) launches
+bool profiling();
+void profile_mark(hipStream_t st, int kind, bool begin);
+}  // namespace gv
