@@ -120,7 +120,7 @@ class Model:
         self.C, self.d, self.D = C.value, d.value, D.value
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.gv_model_destroy(self._h)
             self._h = None
 
@@ -153,7 +153,7 @@ class Index:
         self.n, self.C, self.d, self.d_pad, self.fmt = n.value, C.value, d.value, dp.value, f.value
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.gv_index_destroy(self._h)
             self._h = None
 

@@ -90,14 +90,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
     __syncthreads();
   }
 
-  // D layout of the 16x16 block: lane holds column lane%16, rows 4*(lane/16) + r
+  // D layout of the 16x16 FP64 block: register r of a lane holds column lane%16,
+  // row lane/16 + 4r (the rows of one lane are interleaved, unlike the FP32 forms)
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int64_t i = i0 + wi + 16 * x + 4 * (lane >> 4) + r;
+        int64_t i = i0 + wi + 16 * x + (lane >> 4) + 4 * r;
         int64_t j = j0 + wj + 16 * y + (lane & 15);
         if (i >= M || j >= N) continue;
         double v = acc[x][y][r];

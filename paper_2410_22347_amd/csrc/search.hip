@@ -70,6 +70,22 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
 }
 
 // ============================================================================ S2 + S3
+//
+// One workgroup owns a block of queries and a contiguous range ("split") of
+// row tiles; tiles never straddle two clusters, so a tile meets one eager view
+// q_c per query, held in registers as the matrix-core B operand.  Scores leave
+// the accumulators only through a threshold filter: a score below the query's
+// current threshold tau can never enter the top kappa, so only survivors are
+// written, as 64-bit keys (score desc, id asc), to a per-(query, split) buffer
+// of kCap slots.  A buffer close to full is compacted to its kappa best keys and
+// tau is raised to the kappa-th score.  At the end each buffer keeps at most
+// kappa keys; a tree of merge launches reduces the lists to the final kappa.
+//
+// Threshold cascade: a scan over every s-th tile (a uniform sample of the
+// grouped rows) yields, per query, the kappa-th best score of the sample -- a
+// valid lower bound of the kappa-th best score of the whole database.  Seeding
+// the next, denser scan with it keeps the survivors near kappa * s per query
+// instead of kappa * ln(rows) per split.  The last scan covers every tile.
 namespace {
 
 constexpr int kCap = 2048;  // candidate slots per (query, split)
@@ -81,19 +97,22 @@ struct ScoreArgs {
   const int64_t* offsets; // C + 1
   const uint8_t* qhat;    // m x C x dp, storage format
   const float* qscale;    // m x C
+  const float* tau_init;  // m seed thresholds, or null (-inf)
   uint64_t* buf;          // m x P x kCap keys
   int32_t* cnt_out;       // m x P
   int64_t m;
   int C, dp, ks, kappa, P, nqb;
+  int stride;             // scan every stride-th tile
   int xcd_map;            // 1: splits are pinned to XCDs (needs P % 8 == 0)
 };
 
 template <int FMT, int KSM, int NB, bool SHARED>
 __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
   using Op = MfmaOp<FMT>;
+  using S = typename Op::S;
   using T = typename Op::T;
   constexpr int QWG = SHARED ? 32 * NB : 4 * 32 * NB;   // queries per workgroup
-  constexpr int RPI = SHARED ? 128 : 32;                // rows per iteration
+  constexpr int RPI = SHARED ? 128 : 32;                // rows per tile
   constexpr int LIMIT = kCap - RPI;                     // compact above this
 
   __shared__ int64_t s_off[257];
@@ -124,8 +143,9 @@ __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
 
   for (int c = tid; c <= C; c += 256) s_off[c] = a.offsets[c];
   for (int i = tid; i < QWG; i += 256) {
+    const int64_t q = q0 + i;
     s_cnt[i] = 0;
-    s_tau[i] = (q0 + i < a.m) ? -INFINITY : INFINITY;
+    s_tau[i] = (q < a.m) ? (a.tau_init ? a.tau_init[q] : -INFINITY) : INFINITY;
   }
   __syncthreads();
   if (tid == 0) {
@@ -134,14 +154,36 @@ __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
   }
   __syncthreads();
   const int64_t ntiles = s_tpre[C];
-  const int64_t t_begin = ntiles * p / a.P, t_end = ntiles * (p + 1) / a.P;
+  const int64_t nvirt = (ntiles + a.stride - 1) / a.stride;
+  const int64_t v_begin = nvirt * p / a.P, v_end = nvirt * (p + 1) / a.P;
 
   const int half = lane >> 5, col = lane & 31;
+  const int64_t kofs = (int64_t)(half * Op::EPL) * Op::EB;  // this lane's byte offset in a k-step
   T bq[NB][KSM];
-  float st[NB];      // s_c * t_{q,c} for this lane's queries
-  float tau_s[NB];   // thresholds in the unscaled accumulator domain
+  float st[NB];      // s_c * t_{q,c} for this lane's queries (times the operand widening)
+  float tau_s[NB];   // thresholds in the accumulator domain
   int cur_c = -1;
 
+  auto locate = [&](int64_t v, int& c, int64_t& row0, int64_t& row_end) {
+    const int64_t tile = v * a.stride;
+    int lo = 0, hi = C - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (s_tpre[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    c = lo;
+    row0 = s_off[c] + (tile - s_tpre[c]) * RPI;
+    row_end = s_off[c + 1];
+  };
+  auto load_rows = [&](S (&dst)[KSM], int64_t row0, int64_t row_end) {
+    const int64_t base = row0 + (SHARED ? wave * 32 : 0);
+    const int64_t r = base + col;
+    const int64_t rr = r < row_end ? r : (base < row_end ? base : row0);
+    const uint8_t* rp = a.xlow + rr * (int64_t)a.dp * Op::EB + kofs;
+#pragma unroll
+    for (int s = 0; s < KSM; ++s)
+      if (s < a.ks) dst[s] = *(const S*)(rp + (int64_t)(s * Op::KM) * Op::EB);
+  };
   auto refresh_tau = [&]() {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
@@ -150,27 +192,36 @@ __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
     }
   };
 
-  for (int64_t tile = t_begin; tile < t_end; ++tile) {
-    // cluster of this tile
-    int lo = 0, hi = C - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (s_tpre[mid] <= tile) lo = mid; else hi = mid - 1;
+  S cur[KSM], nxt[KSM];
+  int c_cur = 0;
+  int64_t r0_cur = 0, re_cur = 0;
+  if (v_begin < v_end) {
+    locate(v_begin, c_cur, r0_cur, re_cur);
+    load_rows(cur, r0_cur, re_cur);
+  }
+
+  for (int64_t v = v_begin; v < v_end; ++v) {
+    // prefetch the next tile's rows while this one is scored
+    int c_nxt = 0;
+    int64_t r0_nxt = 0, re_nxt = 0;
+    if (v + 1 < v_end) {
+      locate(v + 1, c_nxt, r0_nxt, re_nxt);
+      load_rows(nxt, r0_nxt, re_nxt);
     }
-    const int c = lo;
-    const int64_t row0 = s_off[c] + (tile - s_tpre[c]) * RPI, row_end = s_off[c + 1];
+    const int c = c_cur;
+    const int64_t row_end = re_cur;
 
     if (c != cur_c) {
       cur_c = c;
-      const float sc = a.scale[c];
+      const float sc = a.scale[c] * (Op::kScale * Op::kScale > 0.0f ? 1.0f / (Op::kScale * Op::kScale) : 1.0f);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int64_t q = wq0 + nb * 32 + col;
         const bool qv = q < a.m;
-        const uint8_t* qp = a.qhat + ((qv ? q : 0) * C + c) * (int64_t)a.dp * Op::EB;
+        const uint8_t* qp = a.qhat + ((qv ? q : 0) * C + c) * (int64_t)a.dp * Op::EB + kofs;
 #pragma unroll
         for (int s = 0; s < KSM; ++s) {
-          if (s < a.ks && qv) bq[nb][s] = *(const T*)(qp + (int64_t)(s * Op::KM + half * Op::EPL) * Op::EB);
+          if (s < a.ks && qv) bq[nb][s] = Op::cvt(*(const S*)(qp + (int64_t)(s * Op::KM) * Op::EB));
           else bq[nb][s] = zero_op<T>();
         }
         st[nb] = sc * (qv ? a.qscale[q * C + c] : 1.0f);
@@ -178,18 +229,15 @@ __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
       refresh_tau();
     }
 
-    const int64_t base = row0 + (SHARED ? wave * 32 : 0);
+    const int64_t base = r0_cur + (SHARED ? wave * 32 : 0);
     if (base < row_end) {
-      const int64_t r = base + col;
-      const bool rv = r < row_end;
-      const uint8_t* rp = a.xlow + (rv ? r : base) * (int64_t)a.dp * Op::EB;
       f32x16 acc[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x16{0};
 #pragma unroll
       for (int s = 0; s < KSM; ++s) {
         if (s < a.ks) {
-          T av = *(const T*)(rp + (int64_t)(s * Op::KM + half * Op::EPL) * Op::EB);
+          const T av = Op::cvt(cur[s]);
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) acc[nb] = Op::mma(av, bq[nb][s], acc[nb]);
         }
@@ -241,11 +289,17 @@ __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
       for (int i = tid; i < a.kappa; i += 256) qbuf[i] = s_stage[i];
       if (tid == 0) {
         s_cnt[lq] = a.kappa;
-        s_tau[lq] = key_score(kth);
+        s_tau[lq] = fmaxf(s_tau[lq], key_score(kth));
       }
       __syncthreads();
     }
     if (nlist > 0) refresh_tau();
+
+#pragma unroll
+    for (int s = 0; s < KSM; ++s) cur[s] = nxt[s];
+    c_cur = c_nxt;
+    r0_cur = r0_nxt;
+    re_cur = re_nxt;
   }
 
   // ---- final: keep at most kappa keys per (query, split)
@@ -273,13 +327,15 @@ __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
 
 // ---------------------------------------------------------------------------- merge
 // Merge groups of G lists per query into one list of the kappa best keys.
-// Final level writes (ids, scores) sorted by key (score desc, id asc).
+// Final level: either (ids, scores) sorted by key (score desc, id asc), or, for
+// a sampling scan of the cascade, only tau = the kappa-th best score (-inf when
+// fewer than kappa candidates exist).
 constexpr int kMergeG = 16;
 
 __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ in, const int32_t* __restrict__ in_cnt,
                                                int64_t in_stride, int L, int kappa, uint64_t* __restrict__ out,
                                                int32_t* __restrict__ out_cnt, int Lo, int32_t* __restrict__ ids,
-                                               float* __restrict__ scores) {
+                                               float* __restrict__ scores, float* __restrict__ tau_out) {
   __shared__ uint64_t keys[kMergeG * 256];
   __shared__ int32_t s_base[kMergeG + 1];
   __shared__ uint64_t s_stage[256];
@@ -301,6 +357,12 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ in, 
     for (int i = tid; i < nl; i += 256) keys[b + i] = src[i];
   }
   __syncthreads();
+  if (tau_out) {  // sampling scan: only the kappa-th best score matters
+    float tau = -INFINITY;
+    if (total >= kappa) tau = key_score(block_kth(keys, total, kappa, sel));
+    if (tid == 0) tau_out[q] = tau;
+    return;
+  }
   int kept = total;
   if (total > kappa) {
     const uint64_t kth = block_kth(keys, total, kappa, sel);
@@ -314,7 +376,7 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ in, 
     for (int i = tid; i < total; i += 256) s_stage[i] = keys[i];
     __syncthreads();
   }
-  if (Lo > 1 || !ids) {
+  if (!ids) {
     uint64_t* dst = out + (q * Lo + g) * (int64_t)kappa;
     for (int i = tid; i < kept; i += 256) dst[i] = s_stage[i];
     if (tid == 0) out_cnt[q * Lo + g] = kept;
@@ -345,14 +407,14 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ in, 
   }
 }
 
-// choose the launch shape of S2/S3
+// choose the launch shape of S2/S3 for a scan over `rows` rows
 struct Shape {
   bool shared;
   int nb;
   int P;
 };
 
-Shape choose_shape(int fmt, int64_t m, int64_t n, int C) {
+Shape choose_shape(int fmt, int64_t m, int64_t rows, int C) {
   Shape sh;
   const int qpw_override = tuned_qpw();
   const int p_override = tuned_splits();
@@ -366,13 +428,12 @@ Shape choose_shape(int fmt, int64_t m, int64_t n, int C) {
   } else {
     sh = {false, 4, 0};
   }
-  if (fmt == GV_FP32) {
-    sh.nb = 1;
-  }
+  if (fmt == GV_FP32) sh.nb = 1;
+  if (sh.shared && sh.nb == 4) sh.nb = 2;
   const int qwg = sh.shared ? 32 * sh.nb : 128 * sh.nb;
   const int64_t nqb = (m + qwg - 1) / qwg;
   const int rpi = sh.shared ? 128 : 32;
-  const int64_t ntiles = n / rpi + C;
+  const int64_t ntiles = rows / rpi + C;
   int P;
   if (p_override > 0) {
     P = p_override;
@@ -423,91 +484,123 @@ gv_status dispatch_ks(int ks, const Shape& sh, const ScoreArgs& args, hipStream_
   return GV_EUNSUPPORTED;
 }
 
+// sampling strides of the threshold cascade, coarsest first, ending with 1
+std::vector<int> cascade(int64_t m, int64_t n, int kappa) {
+  std::vector<int> s{1};
+  if (m < 8) return s;
+  const int64_t min_rows = 64LL * kappa;
+  for (int64_t stride = 16; n / stride >= min_rows && stride <= 4096; stride *= 16) s.insert(s.begin(), (int)stride);
+  return s;
+}
+
 }  // namespace
 
 gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t, int64_t m, int kappa,
                           int32_t* cand_ids, float* cand_scores, hipStream_t st) {
   if (m == 0) return GV_OK;
   const int fmt = idx->fmt;
-  const Shape sh = choose_shape(fmt, m, idx->n, idx->C);
-  const int qwg = sh.shared ? 32 * sh.nb : 128 * sh.nb;
-  const int64_t nqb = (m + qwg - 1) / qwg;
-  const int P = sh.P;
   const int km = (fmt == GV_FP32) ? 2 : 16;
-  ScoreArgs args;
-  args.xlow = (const uint8_t*)idx->xlow;
-  args.ids = idx->ids;
-  args.scale = idx->scale;
-  args.offsets = idx->offsets;
-  args.qhat = (const uint8_t*)qhat;
-  args.qscale = t;
-  args.m = m;
-  args.C = idx->C;
-  args.dp = idx->dp;
-  args.ks = idx->dp / km;
-  args.kappa = kappa;
-  args.P = P;
-  args.nqb = (int)nqb;
-  args.xcd_map = (nqb > 1 && P % 8 == 0) ? 1 : 0;
+  const std::vector<int> levels = cascade(m, idx->n, kappa);
 
-  const int64_t nlists = m * P;
+  // one scratch allocation sized for the largest level
+  int Pmax = 1;
+  for (int s : levels) Pmax = std::max(Pmax, choose_shape(fmt, m, idx->n / s, idx->C).P);
+  const int64_t nl_max = m * Pmax;
   uint64_t* buf = nullptr;
   int32_t* cnt = nullptr;
-  GV_HIP(hipMallocAsync((void**)&buf, sizeof(uint64_t) * nlists * kCap, st));
-  GV_HIP(hipMallocAsync((void**)&cnt, sizeof(int32_t) * nlists, st));
-  args.buf = buf;
-  args.cnt_out = cnt;
-  const int64_t grid64 = nqb * P;
+  float* tau[2] = {nullptr, nullptr};
+  uint64_t* lv_keys[2] = {nullptr, nullptr};
+  int32_t* lv_cnt[2] = {nullptr, nullptr};
+  GV_HIP(hipMallocAsync((void**)&buf, sizeof(uint64_t) * nl_max * kCap, st));
+  GV_HIP(hipMallocAsync((void**)&cnt, sizeof(int32_t) * nl_max, st));
   gv_status s = GV_OK;
-  if (grid64 > 0x7fffffff) s = GV_EUNSUPPORTED;
-  const unsigned grid = (unsigned)grid64;
-  if (s == GV_OK) {
-    profile_mark(st, 0, true);
+  if (levels.size() > 1) {
+    if (hipMallocAsync((void**)&tau[0], sizeof(float) * m, st) != hipSuccess ||
+        hipMallocAsync((void**)&tau[1], sizeof(float) * m, st) != hipSuccess)
+      s = GV_ENOMEM;
+  }
+  const int Lo_max = (Pmax + kMergeG - 1) / kMergeG;
+  if (s == GV_OK && Lo_max > 1) {
+    for (int i = 0; i < 2; ++i)
+      if (hipMallocAsync((void**)&lv_keys[i], sizeof(uint64_t) * m * Lo_max * kappa, st) != hipSuccess ||
+          hipMallocAsync((void**)&lv_cnt[i], sizeof(int32_t) * m * Lo_max, st) != hipSuccess)
+        s = GV_ENOMEM;
+  }
+
+  const float* tau_in = nullptr;
+  for (size_t li = 0; li < levels.size() && s == GV_OK; ++li) {
+    const int stride = levels[li];
+    const bool last = li + 1 == levels.size();
+    const Shape sh = choose_shape(fmt, m, idx->n / stride, idx->C);
+    const int qwg = sh.shared ? 32 * sh.nb : 128 * sh.nb;
+    const int64_t nqb = (m + qwg - 1) / qwg;
+    const int P = sh.P;
+    ScoreArgs args;
+    args.xlow = (const uint8_t*)idx->xlow;
+    args.ids = idx->ids;
+    args.scale = idx->scale;
+    args.offsets = idx->offsets;
+    args.qhat = (const uint8_t*)qhat;
+    args.qscale = t;
+    args.tau_init = tau_in;
+    args.buf = buf;
+    args.cnt_out = cnt;
+    args.m = m;
+    args.C = idx->C;
+    args.dp = idx->dp;
+    args.ks = idx->dp / km;
+    args.kappa = kappa;
+    args.P = P;
+    args.nqb = (int)nqb;
+    args.stride = stride;
+    args.xcd_map = (nqb > 1 && P % 8 == 0) ? 1 : 0;
+    const int64_t grid64 = nqb * P;
+    if (grid64 > 0x7fffffff) {
+      s = GV_EUNSUPPORTED;
+      break;
+    }
+    const unsigned grid = (unsigned)grid64;
+    if (last) profile_mark(st, 0, true);
     switch (fmt) {
       case GV_FP32: s = dispatch_ks<GV_FP32>(args.ks, sh, args, st, grid); break;
       case GV_FP16: s = dispatch_ks<GV_FP16>(args.ks, sh, args, st, grid); break;
       case GV_BF16: s = dispatch_ks<GV_BF16>(args.ks, sh, args, st, grid); break;
       default: s = dispatch_ks<GV_FP8_E4M3>(args.ks, sh, args, st, grid); break;
     }
-    profile_mark(st, 0, false);
-  }
-  // tree merge of the m x P partial lists
-  uint64_t* lv_keys[2] = {nullptr, nullptr};
-  int32_t* lv_cnt[2] = {nullptr, nullptr};
-  if (s == GV_OK) {
+    if (last) profile_mark(st, 0, false);
+    if (s != GV_OK) break;
+
+    // tree merge of the m x P partial lists
+    float* tau_out = last ? nullptr : tau[li & 1];
     const uint64_t* in = buf;
     const int32_t* in_cnt = cnt;
     int64_t in_stride = kCap;
     int L = P;
     int which = 0;
-    profile_mark(st, 1, true);
+    if (last) profile_mark(st, 1, true);
     while (true) {
       const int Lo = (L + kMergeG - 1) / kMergeG;
       if (Lo == 1) {
         hipLaunchKernelGGL(k_merge, dim3((unsigned)m), dim3(256), 0, st, in, in_cnt, in_stride, L, kappa,
-                           (uint64_t*)nullptr, (int32_t*)nullptr, 1, cand_ids, cand_scores);
-        profile_mark(st, 1, false);
+                           (uint64_t*)nullptr, (int32_t*)nullptr, 1, last ? cand_ids : (int32_t*)nullptr,
+                           last ? cand_scores : (float*)nullptr, tau_out);
         break;
       }
-      if (!lv_keys[which]) {
-        if (hipMallocAsync((void**)&lv_keys[which], sizeof(uint64_t) * m * Lo * kappa, st) != hipSuccess ||
-            hipMallocAsync((void**)&lv_cnt[which], sizeof(int32_t) * m * Lo, st) != hipSuccess) {
-          s = GV_ENOMEM;
-          break;
-        }
-      }
       hipLaunchKernelGGL(k_merge, dim3((unsigned)(m * Lo)), dim3(256), 0, st, in, in_cnt, in_stride, L, kappa,
-                         lv_keys[which], lv_cnt[which], Lo, (int32_t*)nullptr, (float*)nullptr);
+                         lv_keys[which], lv_cnt[which], Lo, (int32_t*)nullptr, (float*)nullptr, (float*)nullptr);
       in = lv_keys[which];
       in_cnt = lv_cnt[which];
       in_stride = kappa;
       L = Lo;
       which ^= 1;
     }
+    if (last) profile_mark(st, 1, false);
+    tau_in = tau_out;
   }
   for (int i = 0; i < 2; ++i) {
     if (lv_keys[i]) (void)hipFreeAsync(lv_keys[i], st);
     if (lv_cnt[i]) (void)hipFreeAsync(lv_cnt[i], st);
+    if (tau[i]) (void)hipFreeAsync(tau[i], st);
   }
   GV_HIP(hipFreeAsync(buf, st));
   GV_HIP(hipFreeAsync(cnt, st));

@@ -13,32 +13,70 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Per-format operand of v_mfma_f32_32x32x{16,2}: each lane holds EPL
 // consecutive k of one row (A) or one query (B); lanes 32..63 hold the next EPL.
+// S is the stored type loaded from memory, T the matrix-core operand, cvt the
+// (exact) conversion and kScale the factor cvt applies to each value.
+//
+// FP8-E4M3 storage is widened to FP16 in registers: placing the sign in bit 15
+// and the exponent and fraction fields in bits 7..13 gives, for every finite
+// E4M3 code (normal or subnormal), exactly the E4M3 value times 2^-8.  The
+// FP16 matrix core then forms exact products with FP32 accumulation.  (With
+// the dedicated FP8 x FP8 matrix-core form, scores fell outside the FP32
+// forward-error bound in the parity tests.)
 template <int FMT>
 struct MfmaOp;
 
 template <>
 struct MfmaOp<GV_FP32> {
+  using S = float;
   using T = float;
   static constexpr int KM = 2, EPL = 1, EB = 4;
+  static constexpr float kScale = 1.0f;
+  __device__ static inline T cvt(S v) { return v; }
   __device__ static inline f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
 };
 template <>
 struct MfmaOp<GV_FP16> {
+  using S = f16x8;
   using T = f16x8;
   static constexpr int KM = 16, EPL = 8, EB = 2;
+  static constexpr float kScale = 1.0f;
+  __device__ static inline T cvt(S v) { return v; }
   __device__ static inline f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
 };
 template <>
 struct MfmaOp<GV_BF16> {
+  using S = bf16x8;
   using T = bf16x8;
   static constexpr int KM = 16, EPL = 8, EB = 2;
+  static constexpr float kScale = 1.0f;
+  __device__ static inline T cvt(S v) { return v; }
   __device__ static inline f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
 };
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// two E4M3 bytes (bits 0..7 and 8..15 of w) -> two FP16 lanes, value * 2^-8
+__device__ inline uint32_t e4m3x2_to_f16x2(uint32_t w) {
+  const uint32_t e = ((w << 8) & 0x0000FF00u) | ((w << 16) & 0xFF000000u);
+  return (e & 0x80008000u) | ((e >> 1) & 0x3F803F80u);
+}
+
 template <>
 struct MfmaOp<GV_FP8_E4M3> {
-  using T = long;
+  using S = u32x2;
+  using T = f16x8;
   static constexpr int KM = 16, EPL = 8, EB = 1;
-  __device__ static inline f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0); }
+  static constexpr float kScale = 0.00390625f;  // 2^-8
+  __device__ static inline T cvt(S v) {
+    u32x4 h;
+    h[0] = e4m3x2_to_f16x2(v[0]);
+    h[1] = e4m3x2_to_f16x2(v[0] >> 16);
+    h[2] = e4m3x2_to_f16x2(v[1]);
+    h[3] = e4m3x2_to_f16x2(v[1] >> 16);
+    return __builtin_bit_cast(T, h);
+  }
+  __device__ static inline f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
 };
 
 template <typename T>
