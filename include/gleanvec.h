@@ -164,7 +164,7 @@ void gv_model_destroy(gv_model* model);
 gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format fmt,
                     int32_t copy_X, void* stream, gv_index** out);
 
-/* Shape of an index: rows, clusters, reduced dim, padded row length (elements), format. */
+/* Shape of an index: rows, clusters, reduced dim, padded row length (see gv_padded_dim), format. */
 gv_status gv_index_shape(const gv_index* index, int64_t* n, int32_t* C, int32_t* d,
                          int32_t* d_pad, int32_t* fmt);
 
@@ -172,7 +172,8 @@ gv_status gv_index_shape(const gv_index* index, int64_t* n, int32_t* C, int32_t*
  * gv_index_export -- host copies of the index (any pointer may be NULL):
  * tags (n, uint8, original order), offsets (C + 1, grouped segment starts),
  * ids (n, int32, original id of each grouped position), xlow (n x d_pad
- * elements of the storage format, raw bits, grouped order, zero padded),
+ * elements of the storage format, raw bits, grouped order, zero padded;
+ * d_pad = gv_padded_dim(d)),
  * scale (C, FP32 power-of-two s_c).
  */
 gv_status gv_index_export(const gv_index* index, uint8_t* tags, int64_t* offsets, int32_t* ids,
@@ -210,7 +211,7 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
 /*
  * gv_project -- stage S1 alone (Algorithm 4, preprocess).
  * Q device m x D FP32.  qc device m x C x d_pad FP32 (may be NULL): q_c,
- * zero padded.  t device m x C FP32: the scales.  qhat device m x C x d_pad
+ * zero padded, d_pad = gv_padded_dim(d).  t device m x C FP32: the scales.  qhat device m x C x d_pad
  * elements of `fmt` (raw bits, zero padded).  Errors as gv_search.
  */
 gv_status gv_project(const gv_model* model, gv_format fmt, const float* Q, int64_t m,
@@ -239,10 +240,19 @@ gv_status gv_rerank(const gv_index* index, const float* Q, int64_t m, const int3
 /*
  * gv_search_tuning -- override the launch shape of S2/S3 for the calling
  * thread's following searches (0 restores the automatic choice):
- * splits = number of database splits P, qpw = queries per wavefront (32, 64
- * or 128).  Results do not depend on these; only speed does.
+ * splits = row ranges per query block (1..4096), qpw = queries per wavefront
+ * (32, 64 or 128), cap = candidate slots per (query, row range) before a
+ * compaction to the kappa best (512..2048, must exceed kappa + 32).  Results
+ * do not depend on these; only speed does.  Errors: GV_EINVAL.
  */
-gv_status gv_search_tuning(int32_t splits, int32_t qpw);
+gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap);
+
+/*
+ * gv_padded_dim -- the padded row length d_pad used for a reduced dimension d:
+ * the smallest of 32, 64, 128, 160, 192, 256 that is >= d (gv_project and
+ * gv_index_export lay rows out with it).  Returns 0 for d < 1.
+ */
+int32_t gv_padded_dim(int32_t d);
 
 /*
  * gv_profile_enable / gv_profile_read -- measurement hooks for benchmarks.

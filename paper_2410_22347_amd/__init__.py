@@ -28,6 +28,7 @@ EXPORTED = [
     "gv_model_export", "gv_model_stats", "gv_model_destroy", "gv_encode", "gv_index_shape",
     "gv_index_export", "gv_index_destroy", "gv_search", "gv_project", "gv_score_topk",
     "gv_rerank", "gv_search_tuning", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
+    "gv_padded_dim",
 ]
 
 
@@ -76,7 +77,8 @@ _sig("gv_search", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_project", [_vp, ctypes.c_int, _vp, _i64, _vp, _vp, _vp, _vp])
 _sig("gv_score_topk", [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp])
 _sig("gv_rerank", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
-_sig("gv_search_tuning", [_i32, _i32])
+_sig("gv_search_tuning", [_i32, _i32, _i32])
+_sig("gv_padded_dim", [_i32], _i32)
 _sig("gv_host_eigh", [_i32, _vp, _vp, _vp])
 _sig("gv_profile_enable", [_i32])
 _sig("gv_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
@@ -226,7 +228,7 @@ def project(model: Model, fmt, Q, want_qc: bool = True):
     _dev_f32(Q)
     f = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
     m = Q.shape[0]
-    dp = (model.d + 15) // 16 * 16
+    dp = padded_dim(model.d)
     qc = torch.empty((m, model.C, dp), dtype=torch.float32, device=Q.device) if want_qc else None
     t = torch.empty((m, model.C), dtype=torch.float32, device=Q.device)
     qhat = torch.empty((m, model.C, dp), dtype=_elem_dtype(f), device=Q.device)
@@ -257,8 +259,12 @@ def rerank(index: Index, Q, cand_ids, k: int):
     return ids, sc
 
 
-def search_tuning(splits: int = 0, qpw: int = 0):
-    _check(_lib.gv_search_tuning(splits, qpw), "gv_search_tuning")
+def search_tuning(splits: int = 0, qpw: int = 0, cap: int = 0):
+    _check(_lib.gv_search_tuning(splits, qpw, cap), "gv_search_tuning")
+
+
+def padded_dim(d: int) -> int:
+    return int(_lib.gv_padded_dim(d))
 
 
 def host_eigh(A):

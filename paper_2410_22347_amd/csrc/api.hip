@@ -11,11 +11,12 @@
 namespace gv {
 
 static thread_local std::string g_err;
-static thread_local int g_splits = 0, g_qpw = 0;
+static thread_local int g_splits = 0, g_qpw = 0, g_cap = 0;
 void set_error(const std::string& msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 int tuned_splits() { return g_splits; }
 int tuned_qpw() { return g_qpw; }
+int tuned_cap() { return g_cap; }
 
 namespace {
 struct ProfRec {
@@ -267,7 +268,7 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
     x->magic = kIndexMagic;
     x->C = model->C;
     x->d = model->d;
-    x->dp = pad16(model->d);
+    x->dp = pad_dim(model->d);
     x->D = model->D;
     x->fmt = fmt;
     x->n = n;
@@ -282,9 +283,8 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
       gv_index_destroy(x);
       return s;
     };
+    x->n_pad = 0;
     if (hipMalloc(&x->tags, n) != hipSuccess || hipMalloc(&x->offsets, sizeof(int64_t) * (x->C + 1)) != hipSuccess ||
-        hipMalloc(&x->ids, sizeof(int32_t) * n) != hipSuccess ||
-        hipMalloc(&x->xlow, (size_t)n * x->dp * fmt_bytes(fmt)) != hipSuccess ||
         hipMalloc(&x->scale, sizeof(float) * x->C) != hipSuccess) {
       set_error("gv_encode: device allocation failed");
       return fail(GV_ENOMEM);
@@ -321,10 +321,28 @@ gv_status gv_index_shape(const gv_index* x, int64_t* n, int32_t* C, int32_t* d, 
 gv_status gv_index_export(const gv_index* x, uint8_t* tags, int64_t* offsets, int32_t* ids, void* xlow, float* scale) {
   return guarded([&]() -> gv_status {
     if (!valid(x)) return GV_ENOTFIT;
+    // the device keeps padded segments and operand tiles; the export is dense and row-major
+    std::vector<int64_t> roff(x->C + 1, 0);
+    for (int c = 0; c < x->C; ++c) roff[c + 1] = roff[c] + x->h_counts[c];
     if (tags) GV_HIP(hipMemcpy(tags, x->tags, x->n, hipMemcpyDeviceToHost));
-    if (offsets) std::memcpy(offsets, x->h_offsets.data(), sizeof(int64_t) * (x->C + 1));
-    if (ids) GV_HIP(hipMemcpy(ids, x->ids, sizeof(int32_t) * x->n, hipMemcpyDeviceToHost));
-    if (xlow) GV_HIP(hipMemcpy(xlow, x->xlow, (size_t)x->n * x->dp * fmt_bytes(x->fmt), hipMemcpyDeviceToHost));
+    if (offsets) std::memcpy(offsets, roff.data(), sizeof(int64_t) * (x->C + 1));
+    if (ids) {
+      std::vector<int32_t> pid(x->n_pad);
+      GV_HIP(hipMemcpy(pid.data(), x->ids, sizeof(int32_t) * x->n_pad, hipMemcpyDeviceToHost));
+      for (int c = 0; c < x->C; ++c)
+        for (int64_t i = 0; i < x->h_counts[c]; ++i) ids[roff[c] + i] = pid[x->h_offsets[c] + i];
+    }
+    if (xlow) {
+      const int eb = fmt_bytes(x->fmt), km = fmt_km(x->fmt), epl = fmt_epl(x->fmt);
+      std::vector<uint8_t> tiles((size_t)x->n_pad * x->dp * eb);
+      GV_HIP(hipMemcpy(tiles.data(), x->xlow, tiles.size(), hipMemcpyDeviceToHost));
+      uint8_t* out = (uint8_t*)xlow;
+      for (int c = 0; c < x->C; ++c)
+        for (int64_t i = 0; i < x->h_counts[c]; ++i)
+          for (int j = 0; j < x->dp; ++j)
+            std::memcpy(out + ((roff[c] + i) * x->dp + j) * eb,
+                        tiles.data() + tiled_offset(x->h_offsets[c] + i, j, x->dp, km, epl) * eb, eb);
+    }
     if (scale) GV_HIP(hipMemcpy(scale, x->scale, sizeof(float) * x->C, hipMemcpyDeviceToHost));
     return GV_OK;
   });
@@ -415,13 +433,17 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
   });
 }
 
-gv_status gv_search_tuning(int32_t splits, int32_t qpw) {
+gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap) {
   if (splits < 0 || splits > 4096) return GV_EINVAL;
   if (qpw != 0 && qpw != 32 && qpw != 64 && qpw != 128) return GV_EINVAL;
+  if (cap != 0 && (cap < 512 || cap > 2048)) return GV_EINVAL;
   g_splits = splits;
   g_qpw = qpw;
+  g_cap = cap;
   return GV_OK;
 }
+
+int32_t gv_padded_dim(int32_t d) { return d >= 1 ? pad_dim(d) : 0; }
 
 gv_status gv_profile_enable(int32_t on) {
   g_prof_on = on != 0;

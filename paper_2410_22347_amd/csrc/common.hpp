@@ -44,8 +44,33 @@ void clear_error();
 
 // ---------------------------------------------------------------- formats
 inline int fmt_bytes(int f) { return f == GV_FP32 ? 4 : (f == GV_FP8_E4M3 ? 1 : 2); }
-// reduced rows are padded with zeros to a multiple of 16 elements
-inline int pad16(int d) { return (d + 15) / 16 * 16; }
+
+// Matrix-core operand tiling of the stored reduced vectors.  Rows are grouped
+// by cluster, each cluster's segment padded to a multiple of 32 rows.  A tile
+// is 32 consecutive rows; within it, k-step s (KM reduced dimensions) forms a
+// block of 64 lanes x EPL elements where lane l holds row l % 32, dimensions
+// s*KM + (l / 32)*EPL ... + EPL - 1.  A wavefront thus loads the A operand of
+// one k-step as one contiguous block.  FP32: KM = 2, EPL = 1; FP16, BF16 and
+// FP8: KM = 16, EPL = 8.
+inline int fmt_km(int f) { return f == GV_FP32 ? 2 : 16; }
+inline int fmt_epl(int f) { return f == GV_FP32 ? 1 : 8; }
+constexpr int kTileRows = 32;
+__host__ __device__ inline int64_t tiled_offset(int64_t p, int j, int dp, int km, int epl) {
+  const int64_t t = p / kTileRows;
+  const int i = (int)(p - t * kTileRows);
+  const int s = j / km, w = j - s * km;
+  const int half = w / epl, e = w - half * epl;
+  const int lane = i + kTileRows * half;
+  return (t * (dp / km) + s) * (int64_t)(64 * epl) + (int64_t)lane * epl + e;  // in elements
+}
+// Reduced rows (and query views) are zero-padded to one of a few lengths so
+// the scoring kernel runs a fully unrolled, branch-free matrix-core chain.
+inline int pad_dim(int d) {
+  const int sizes[] = {32, 64, 128, 160, 192, 256};
+  for (int s : sizes)
+    if (d <= s) return s;
+  return (d + 15) / 16 * 16;  // beyond 256: rejected by encode
+}
 
 // Scale targets: the block's largest magnitude is mapped into (T/2, T].
 inline double scale_target(int f) {
@@ -154,16 +179,18 @@ struct gv_model {
 struct gv_index {
   uint64_t magic;
   int C, d, dp, D, fmt;
-  int64_t n;
+  int64_t n;       // database rows
+  int64_t n_pad;   // stored rows: every cluster segment padded to a multiple of 32
   int device;
-  uint8_t* tags;     // device n
-  int64_t* offsets;  // device C+1
-  int32_t* ids;      // device n
-  void* xlow;        // device n x dp elements of fmt
+  uint8_t* tags;     // device n, cluster of each original row
+  int64_t* offsets;  // device C+1, padded segment starts (multiples of 32)
+  int32_t* ids;      // device n_pad, original id of each stored row, -1 for padding
+  void* xlow;        // device n_pad x dp elements of fmt, matrix-core tiled
   float* scale;      // device C
   const float* X;    // device n x D (owned if own_X)
   bool own_X;
-  std::vector<int64_t> h_offsets;
+  std::vector<int64_t> h_offsets;  // padded segment starts
+  std::vector<int64_t> h_counts;   // rows per cluster
 };
 
 constexpr uint64_t kModelMagic = 0x474C45414E4D4F44ull;  // "GLEANMOD"
@@ -212,6 +239,7 @@ void eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vec
 
 int tuned_splits();
 int tuned_qpw();
+int tuned_cap();
 
 // benchmark hooks: events around scoring (kind 0) and merge (kind 1) launches
 bool profiling();

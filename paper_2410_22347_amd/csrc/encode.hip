@@ -3,12 +3,13 @@
 //
 // Layout in HBM (all device memory owned by the index):
 //   tags[n]            uint8, cluster of each original row;
-//   offsets[C+1]       int64, start of each cluster's segment in grouped order;
-//   ids[n]             int32, original row id of each grouped position (stable:
-//                      increasing inside a segment);
-//   xlow[n][d_pad]     storage format, grouped order, rows zero-padded to a
-//                      multiple of 16 elements so every matrix-core operand load
-//                      is aligned and full width;
+//   offsets[C+1]       int64, start of each cluster's stored segment; segments
+//                      are padded to a multiple of 32 rows (one tile);
+//   ids[n_pad]         int32, original row id of each stored row (stable:
+//                      increasing inside a segment), -1 for padding rows;
+//   xlow[n_pad][d_pad] storage format, zero padded, in matrix-core operand
+//                      tiles (see tiled_offset): one k-step of a 32-row tile is
+//                      one contiguous block that a wavefront loads in one go;
 //   scale[C]           FP32 power-of-two s_c; the stored value is rnd(v / s_c);
 //   X[n][D]            FP32 original vectors for the rerank (copied or borrowed).
 // The grouped layout replaces the paper's interleaved (tag, x_low) pairs: a
@@ -87,35 +88,37 @@ __global__ void k_segment_amax(const float* __restrict__ v, int d, const int64_t
 }
 
 template <int FMT>
-__global__ void k_quantize(const float* __restrict__ v, int64_t n, int d, int dp, const int64_t* __restrict__ off,
-                           int C, const float* __restrict__ scale, void* __restrict__ out) {
+__global__ void k_quantize(const float* __restrict__ v, int64_t n_pad, int d, int dp, const int64_t* __restrict__ off,
+                           int C, const float* __restrict__ scale, const int32_t* __restrict__ ids,
+                           void* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * dp) return;
+  if (e >= n_pad * dp) return;
   const int64_t p = e / dp;
   const int j = (int)(e - p * dp);
-  // cluster of grouped row p: last c with off[c] <= p
+  // cluster of stored row p: last c with off[c] <= p
   int lo = 0, hi = C - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (off[mid] <= p) lo = mid; else hi = mid - 1;
   }
-  const float x = (j < d) ? v[p * d + j] : 0.0f;
+  const float x = (j < d && ids[p] >= 0) ? v[p * d + j] : 0.0f;
   const double y = (double)x / (double)scale[lo];  // exact: scale is a power of two
+  const int64_t o = tiled_offset(p, j, dp, FMT == GV_FP32 ? 2 : 16, FMT == GV_FP32 ? 1 : 8);
   if (FMT == GV_FP32) {
-    ((float*)out)[e] = x;
+    ((float*)out)[o] = x;
   } else if (FMT == GV_FP16) {
-    ((uint16_t*)out)[e] = to_fp16(y);
+    ((uint16_t*)out)[o] = to_fp16(y);
   } else if (FMT == GV_BF16) {
-    ((uint16_t*)out)[e] = to_bf16(y);
+    ((uint16_t*)out)[o] = to_bf16(y);
   } else {
-    ((uint8_t*)out)[e] = to_fp8(y);
+    ((uint8_t*)out)[o] = to_fp8(y);
   }
 }
 
 }  // namespace
 
 gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt, hipStream_t st, gv_index* idx) {
-  const int C = model->C, d = model->d, D = model->D, dp = pad16(d);
+  const int C = model->C, d = model->d, D = model->D, dp = pad_dim(d);
 
   // ------------------------------------------------ tags, FP64 arg-max (Eq. 9)
   {
@@ -138,10 +141,9 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
     GV_HIP(hipGetLastError());
   }
 
-  // ------------------------------------------------ stable grouping by tag
+  // ------------------------------------------------ stable grouping by tag, padded segments
   const int64_t nb = (n + kBlockRows - 1) / kBlockRows;
   int64_t* ids64 = nullptr;
-  GV_HIP(hipMallocAsync((void**)&ids64, sizeof(int64_t) * n, st));
   {
     int32_t* hist = nullptr;
     int64_t* base = nullptr;
@@ -154,15 +156,24 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
     GV_HIP(hipStreamSynchronize(st));
     std::vector<int64_t> h_base((size_t)nb * C);
     idx->h_offsets.assign(C + 1, 0);
+    idx->h_counts.assign(C, 0);
     int64_t run = 0;
     for (int c = 0; c < C; ++c) {
       idx->h_offsets[c] = run;
+      int64_t cnt = 0;
       for (int64_t b = 0; b < nb; ++b) {
-        h_base[(size_t)c * nb + b] = run;
-        run += h_hist[(size_t)b * C + c];
+        h_base[(size_t)c * nb + b] = run + cnt;
+        cnt += h_hist[(size_t)b * C + c];
       }
+      idx->h_counts[c] = cnt;
+      run += (cnt + kTileRows - 1) / kTileRows * kTileRows;
     }
     idx->h_offsets[C] = run;
+    idx->n_pad = run;
+    GV_HIP(hipMalloc((void**)&idx->ids, sizeof(int32_t) * std::max<int64_t>(run, 1)));
+    GV_HIP(hipMalloc(&idx->xlow, (size_t)std::max<int64_t>(run, 1) * dp * fmt_bytes(fmt)));
+    GV_HIP(hipMallocAsync((void**)&ids64, sizeof(int64_t) * std::max<int64_t>(run, 1), st));
+    GV_HIP(hipMemsetAsync(idx->ids, 0xFF, sizeof(int32_t) * run, st));  // -1: padding
     GV_HIP(hipMemcpyAsync(base, h_base.data(), sizeof(int64_t) * nb * C, hipMemcpyHostToDevice, st));
     GV_HIP(hipMemcpyAsync(idx->offsets, idx->h_offsets.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nb), dim3(64), 0, st, idx->tags, n, C, base, nb, idx->ids,
@@ -171,12 +182,14 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
     GV_HIP(hipFreeAsync(hist, st));
     GV_HIP(hipFreeAsync(base, st));
   }
+  const int64_t n_pad = idx->n_pad;
 
   // ------------------------------------------------ x_low = fl32(B_c x), FP64 accumulation (Eq. 10)
   float* v = nullptr;
-  GV_HIP(hipMallocAsync((void**)&v, sizeof(float) * n * d, st));
+  GV_HIP(hipMallocAsync((void**)&v, sizeof(float) * std::max<int64_t>(n_pad, 1) * d, st));
+  GV_HIP(hipMemsetAsync(v, 0, sizeof(float) * n_pad * d, st));
   for (int c = 0; c < C; ++c) {
-    const int64_t a = idx->h_offsets[c], nc = idx->h_offsets[c + 1] - a;
+    const int64_t a = idx->h_offsets[c], nc = idx->h_counts[c];
     if (nc == 0) continue;
     GemmOperand<float> xo{X, D, ids64 + a, Layout::RowMajor};
     GemmOperand<double> bo{model->B + (int64_t)c * d * D, D, nullptr, Layout::RowMajor};
@@ -199,20 +212,24 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
     h_scale[c] = pow2_scale(a, scale_target(fmt));
   }
   GV_HIP(hipMemcpyAsync(idx->scale, h_scale.data(), sizeof(float) * C, hipMemcpyHostToDevice, st));
-  const int64_t total = n * dp;
+  const int64_t total = n_pad * dp;
   const unsigned grid = (unsigned)((total + 255) / 256);
   switch (fmt) {
     case GV_FP32:
-      hipLaunchKernelGGL(k_quantize<GV_FP32>, dim3(grid), dim3(256), 0, st, v, n, d, dp, idx->offsets, C, idx->scale, idx->xlow);
+      hipLaunchKernelGGL(k_quantize<GV_FP32>, dim3(grid), dim3(256), 0, st, v, n_pad, d, dp, idx->offsets, C,
+                         idx->scale, idx->ids, idx->xlow);
       break;
     case GV_FP16:
-      hipLaunchKernelGGL(k_quantize<GV_FP16>, dim3(grid), dim3(256), 0, st, v, n, d, dp, idx->offsets, C, idx->scale, idx->xlow);
+      hipLaunchKernelGGL(k_quantize<GV_FP16>, dim3(grid), dim3(256), 0, st, v, n_pad, d, dp, idx->offsets, C,
+                         idx->scale, idx->ids, idx->xlow);
       break;
     case GV_BF16:
-      hipLaunchKernelGGL(k_quantize<GV_BF16>, dim3(grid), dim3(256), 0, st, v, n, d, dp, idx->offsets, C, idx->scale, idx->xlow);
+      hipLaunchKernelGGL(k_quantize<GV_BF16>, dim3(grid), dim3(256), 0, st, v, n_pad, d, dp, idx->offsets, C,
+                         idx->scale, idx->ids, idx->xlow);
       break;
     default:
-      hipLaunchKernelGGL(k_quantize<GV_FP8_E4M3>, dim3(grid), dim3(256), 0, st, v, n, d, dp, idx->offsets, C, idx->scale, idx->xlow);
+      hipLaunchKernelGGL(k_quantize<GV_FP8_E4M3>, dim3(grid), dim3(256), 0, st, v, n_pad, d, dp, idx->offsets, C,
+                         idx->scale, idx->ids, idx->xlow);
       break;
   }
   GV_HIP(hipGetLastError());

@@ -1,0 +1,15 @@
+// Instantiation of the scoring kernel for fp16 storage.
+#include "search_kernels.hpp"
+
+namespace gv {
+
+template <int FMT, int MODE>
+gv_status dispatch_scan(int dp, const scan::Shape& sh, const scan::ScoreArgs& args, hipStream_t st) {
+  return scan::dispatch_ks<FMT, MODE>(dp, sh, args, st);
+}
+
+template gv_status dispatch_scan<GV_FP16, scan::kMain>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
+template gv_status dispatch_scan<GV_FP16, scan::kPilot>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
+template gv_status dispatch_scan<GV_FP16, scan::kDense>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
+
+}  // namespace gv

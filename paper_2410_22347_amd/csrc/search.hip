@@ -6,7 +6,7 @@
 #include <cmath>
 #include <vector>
 
-#include "search_common.hpp"
+#include "search_kernels.hpp"
 
 namespace gv {
 
@@ -38,21 +38,49 @@ __global__ void k_quant_queries(float* __restrict__ qc, int64_t m, int C, int d,
   }
 }
 
+// q_c = fl32(A_c q) for a few queries: one wavefront per row of the stacked A
+// (C*d rows), the row read once and dotted with every query (FP64 accumulation).
+// Used when the batch is too small to fill the GEMM tiles.
+constexpr int kSmallM = 16;
+__global__ __launch_bounds__(256) void k_project_small(const float* __restrict__ Q, int64_t m, int D,
+                                                       const double* __restrict__ A, int64_t rows, int d, int dp,
+                                                       int C, float* __restrict__ qc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= rows) return;
+  const double* a = A + j * D;
+  const int64_t c = j / d, jj = j - c * d;
+  for (int64_t i = 0; i < m; ++i) {
+    const float* q = Q + i * D;
+    double s = 0.0;
+    for (int k = lane; k < D; k += 64) s += a[k] * (double)q[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) qc[(i * C + c) * dp + jj] = (float)s;
+  }
+}
+
 }  // namespace
 
 gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m, float* qc, float* t, void* qhat,
                        hipStream_t st) {
-  const int C = model->C, d = model->d, D = model->D, dp = pad16(d);
+  const int C = model->C, d = model->d, D = model->D, dp = pad_dim(d);
   float* tmp = nullptr;
   if (!qc) {
     GV_HIP(hipMallocAsync((void**)&tmp, sizeof(float) * m * C * dp, st));
     qc = tmp;
   }
   // q_c = fl32(A_c q), FP64 accumulation; columns j of the stacked A map to (c, j % d)
-  GemmOperand<float> qo{Q, D, nullptr, Layout::RowMajor};
-  GemmOperand<double> ao{model->A, D, nullptr, Layout::RowMajor};
-  gv_status s = gemm_f64<float, double>(m, (int64_t)C * d, D, qo, ao, Epi::StoreF32Proj,
-                                        GemmOut{qc, (int64_t)C * dp, d, dp, nullptr}, st);
+  gv_status s = GV_OK;
+  if (m <= kSmallM) {
+    const int64_t rows = (int64_t)C * d;
+    hipLaunchKernelGGL(k_project_small, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, Q, m, D, model->A, rows,
+                       d, dp, C, qc);
+  } else {
+    GemmOperand<float> qo{Q, D, nullptr, Layout::RowMajor};
+    GemmOperand<double> ao{model->A, D, nullptr, Layout::RowMajor};
+    s = gemm_f64<float, double>(m, (int64_t)C * d, D, qo, ao, Epi::StoreF32Proj,
+                                GemmOut{qc, (int64_t)C * dp, d, dp, nullptr}, st);
+  }
   if (s == GV_OK) {
     const unsigned grid = (unsigned)((m * C + 3) / 4);
     const double T = scale_target(fmt);
@@ -69,260 +97,46 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
   return GV_OK;
 }
 
-// ============================================================================ S2 + S3
-//
-// One workgroup owns a block of queries and a contiguous range ("split") of
-// row tiles; tiles never straddle two clusters, so a tile meets one eager view
-// q_c per query, held in registers as the matrix-core B operand.  Scores leave
-// the accumulators only through a threshold filter: a score below the query's
-// current threshold tau can never enter the top kappa, so only survivors are
-// written, as 64-bit keys (score desc, id asc), to a per-(query, split) buffer
-// of kCap slots.  A buffer close to full is compacted to its kappa best keys and
-// tau is raised to the kappa-th score.  At the end each buffer keeps at most
-// kappa keys; a tree of merge launches reduces the lists to the final kappa.
-//
-// Threshold cascade: a scan over every s-th tile (a uniform sample of the
-// grouped rows) yields, per query, the kappa-th best score of the sample -- a
-// valid lower bound of the kappa-th best score of the whole database.  Seeding
-// the next, denser scan with it keeps the survivors near kappa * s per query
-// instead of kappa * ln(rows) per split.  The last scan covers every tile.
 namespace {
+using namespace scan;
 
-constexpr int kCap = 2048;  // candidate slots per (query, split)
+// seed[q] = -inf, tau_ord[q] = max, kcount[q] = 0
+__global__ void k_seed_init(int64_t m, float* __restrict__ seed, uint32_t* __restrict__ tau_ord,
+                            int32_t* __restrict__ kcount) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  seed[q] = -INFINITY;
+  tau_ord[q] = 0xFFFFFFFFu;
+  kcount[q] = 0;
+}
 
-struct ScoreArgs {
-  const uint8_t* xlow;    // n x dp, storage format
-  const int32_t* ids;     // grouped position -> original id
-  const float* scale;     // C
-  const int64_t* offsets; // C + 1
-  const uint8_t* qhat;    // m x C x dp, storage format
-  const float* qscale;    // m x C
-  const float* tau_init;  // m seed thresholds, or null (-inf)
-  uint64_t* buf;          // m x P x kCap keys
-  int32_t* cnt_out;       // m x P
-  int64_t m;
-  int C, dp, ks, kappa, P, nqb;
-  int stride;             // scan every stride-th tile
-  int xcd_map;            // 1: splits are pinned to XCDs (needs P % 8 == 0)
-};
+// after a pilot scan: raise the seed when the ranges kept kappa keys in total
+__global__ void k_seed_update(int64_t m, int kappa, float* __restrict__ seed, uint32_t* __restrict__ tau_ord,
+                              int32_t* __restrict__ kcount) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  if (kcount[q] >= kappa) seed[q] = fmaxf(seed[q], unorder_f32(tau_ord[q]));
+  tau_ord[q] = 0xFFFFFFFFu;
+  kcount[q] = 0;
+}
 
-template <int FMT, int KSM, int NB, bool SHARED>
-__global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
-  using Op = MfmaOp<FMT>;
-  using S = typename Op::S;
-  using T = typename Op::T;
-  constexpr int QWG = SHARED ? 32 * NB : 4 * 32 * NB;   // queries per workgroup
-  constexpr int RPI = SHARED ? 128 : 32;                // rows per tile
-  constexpr int LIMIT = kCap - RPI;                     // compact above this
-
-  __shared__ int64_t s_off[257];
-  __shared__ int32_t s_tpre[257];
-  __shared__ int32_t s_cnt[QWG];
-  __shared__ float s_tau[QWG];
-  __shared__ int32_t s_list[QWG];
-  __shared__ int32_t s_nlist;
-  __shared__ uint64_t s_stage[256];
-  __shared__ uint32_t s_kept;
-  __shared__ SelectSmem sel;
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int C = a.C;
-
-  // ---- workgroup -> (query block, split); splits pinned to one XCD when asked
-  int qb, p;
-  if (a.xcd_map) {
-    const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
-    qb = j % a.nqb;
-    p = (j / a.nqb) * 8 + x;
-  } else {
-    qb = blockIdx.x % a.nqb;
-    p = blockIdx.x / a.nqb;
+// after the dense scan: seed = kappa-th best score of the sample (one wavefront per query)
+__global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ dense, int64_t m, int64_t ns,
+                                                      int kappa, float* __restrict__ seed) {
+  __shared__ uint32_t hist[4][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+  if (q >= m) return;
+  const float* row = dense + q * ns;
+  int valid = 0;
+  for (int64_t i = lane; i < ns; i += 64) valid += row[i] != -INFINITY;
+  for (int o = 32; o > 0; o >>= 1) valid += __shfl_xor(valid, o);
+  float tau = -INFINITY;
+  if (valid >= kappa) {
+    auto load = [&](int i) { return make_key(row[i], (uint32_t)i); };
+    tau = key_score(wave_kth(load, (int)ns, kappa, hist[wave]));
   }
-  const int64_t q0 = (int64_t)qb * QWG;
-  const int64_t wq0 = SHARED ? q0 : q0 + wave * 32 * NB;
-
-  for (int c = tid; c <= C; c += 256) s_off[c] = a.offsets[c];
-  for (int i = tid; i < QWG; i += 256) {
-    const int64_t q = q0 + i;
-    s_cnt[i] = 0;
-    s_tau[i] = (q < a.m) ? (a.tau_init ? a.tau_init[q] : -INFINITY) : INFINITY;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    s_tpre[0] = 0;
-    for (int c = 0; c < C; ++c) s_tpre[c + 1] = s_tpre[c] + (int32_t)((s_off[c + 1] - s_off[c] + RPI - 1) / RPI);
-  }
-  __syncthreads();
-  const int64_t ntiles = s_tpre[C];
-  const int64_t nvirt = (ntiles + a.stride - 1) / a.stride;
-  const int64_t v_begin = nvirt * p / a.P, v_end = nvirt * (p + 1) / a.P;
-
-  const int half = lane >> 5, col = lane & 31;
-  const int64_t kofs = (int64_t)(half * Op::EPL) * Op::EB;  // this lane's byte offset in a k-step
-  T bq[NB][KSM];
-  float st[NB];      // s_c * t_{q,c} for this lane's queries (times the operand widening)
-  float tau_s[NB];   // thresholds in the accumulator domain
-  int cur_c = -1;
-
-  auto locate = [&](int64_t v, int& c, int64_t& row0, int64_t& row_end) {
-    const int64_t tile = v * a.stride;
-    int lo = 0, hi = C - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (s_tpre[mid] <= tile) lo = mid; else hi = mid - 1;
-    }
-    c = lo;
-    row0 = s_off[c] + (tile - s_tpre[c]) * RPI;
-    row_end = s_off[c + 1];
-  };
-  auto load_rows = [&](S (&dst)[KSM], int64_t row0, int64_t row_end) {
-    const int64_t base = row0 + (SHARED ? wave * 32 : 0);
-    const int64_t r = base + col;
-    const int64_t rr = r < row_end ? r : (base < row_end ? base : row0);
-    const uint8_t* rp = a.xlow + rr * (int64_t)a.dp * Op::EB + kofs;
-#pragma unroll
-    for (int s = 0; s < KSM; ++s)
-      if (s < a.ks) dst[s] = *(const S*)(rp + (int64_t)(s * Op::KM) * Op::EB);
-  };
-  auto refresh_tau = [&]() {
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int lq = (int)(wq0 - q0) + nb * 32 + col;
-      tau_s[nb] = s_tau[lq] / st[nb];
-    }
-  };
-
-  S cur[KSM], nxt[KSM];
-  int c_cur = 0;
-  int64_t r0_cur = 0, re_cur = 0;
-  if (v_begin < v_end) {
-    locate(v_begin, c_cur, r0_cur, re_cur);
-    load_rows(cur, r0_cur, re_cur);
-  }
-
-  for (int64_t v = v_begin; v < v_end; ++v) {
-    // prefetch the next tile's rows while this one is scored
-    int c_nxt = 0;
-    int64_t r0_nxt = 0, re_nxt = 0;
-    if (v + 1 < v_end) {
-      locate(v + 1, c_nxt, r0_nxt, re_nxt);
-      load_rows(nxt, r0_nxt, re_nxt);
-    }
-    const int c = c_cur;
-    const int64_t row_end = re_cur;
-
-    if (c != cur_c) {
-      cur_c = c;
-      const float sc = a.scale[c] * (Op::kScale * Op::kScale > 0.0f ? 1.0f / (Op::kScale * Op::kScale) : 1.0f);
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int64_t q = wq0 + nb * 32 + col;
-        const bool qv = q < a.m;
-        const uint8_t* qp = a.qhat + ((qv ? q : 0) * C + c) * (int64_t)a.dp * Op::EB + kofs;
-#pragma unroll
-        for (int s = 0; s < KSM; ++s) {
-          if (s < a.ks && qv) bq[nb][s] = Op::cvt(*(const S*)(qp + (int64_t)(s * Op::KM) * Op::EB));
-          else bq[nb][s] = zero_op<T>();
-        }
-        st[nb] = sc * (qv ? a.qscale[q * C + c] : 1.0f);
-      }
-      refresh_tau();
-    }
-
-    const int64_t base = r0_cur + (SHARED ? wave * 32 : 0);
-    if (base < row_end) {
-      f32x16 acc[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x16{0};
-#pragma unroll
-      for (int s = 0; s < KSM; ++s) {
-        if (s < a.ks) {
-          const T av = Op::cvt(cur[s]);
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) acc[nb] = Op::mma(av, bq[nb][s], acc[nb]);
-        }
-      }
-      // epilogue: lane holds query col, rows base + (i%4) + 8*(i/4) + 4*half
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        float mx = -INFINITY;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) mx = fmaxf(mx, acc[nb][i]);
-        if (mx >= tau_s[nb]) {
-          const int lq = (int)(wq0 - q0) + nb * 32 + col;
-          const int64_t q = q0 + lq;
-          uint64_t* qbuf = a.buf + ((q * a.P) + p) * (int64_t)kCap;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int64_t row = base + (i & 3) + 8 * (i >> 2) + 4 * half;
-            if (row < row_end && acc[nb][i] >= tau_s[nb]) {
-              const float score = acc[nb][i] * st[nb];
-              const uint32_t id = (uint32_t)a.ids[row];
-              const int slot = atomicAdd(&s_cnt[lq], 1);
-              qbuf[slot] = make_key(score, id);
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---- compaction of the queries whose buffers are nearly full
-    if (tid == 0) s_nlist = 0;
-    __syncthreads();
-    for (int i = tid; i < QWG; i += 256)
-      if (s_cnt[i] > LIMIT) s_list[atomicAdd(&s_nlist, 1)] = i;
-    __syncthreads();
-    const int nlist = s_nlist;
-    for (int li = 0; li < nlist; ++li) {
-      const int lq = s_list[li];
-      uint64_t* qbuf = a.buf + (((q0 + lq) * a.P) + p) * (int64_t)kCap;
-      const int cnt = s_cnt[lq];
-      const uint64_t kth = block_kth(qbuf, cnt, a.kappa, sel);
-      if (tid == 0) s_kept = 0;
-      __syncthreads();
-      for (int i = tid; i < cnt; i += 256) {
-        uint64_t k = qbuf[i];
-        if (k >= kth) s_stage[atomicAdd(&s_kept, 1u)] = k;
-      }
-      __syncthreads();
-      for (int i = tid; i < a.kappa; i += 256) qbuf[i] = s_stage[i];
-      if (tid == 0) {
-        s_cnt[lq] = a.kappa;
-        s_tau[lq] = fmaxf(s_tau[lq], key_score(kth));
-      }
-      __syncthreads();
-    }
-    if (nlist > 0) refresh_tau();
-
-#pragma unroll
-    for (int s = 0; s < KSM; ++s) cur[s] = nxt[s];
-    c_cur = c_nxt;
-    r0_cur = r0_nxt;
-    re_cur = re_nxt;
-  }
-
-  // ---- final: keep at most kappa keys per (query, split)
-  __syncthreads();
-  for (int lq = 0; lq < QWG; ++lq) {
-    const int64_t q = q0 + lq;
-    if (q >= a.m) break;
-    uint64_t* qbuf = a.buf + ((q * a.P) + p) * (int64_t)kCap;
-    const int cnt = s_cnt[lq];
-    if (cnt > a.kappa) {
-      const uint64_t kth = block_kth(qbuf, cnt, a.kappa, sel);
-      if (tid == 0) s_kept = 0;
-      __syncthreads();
-      for (int i = tid; i < cnt; i += 256) {
-        uint64_t k = qbuf[i];
-        if (k >= kth) s_stage[atomicAdd(&s_kept, 1u)] = k;
-      }
-      __syncthreads();
-      for (int i = tid; i < a.kappa; i += 256) qbuf[i] = s_stage[i];
-      __syncthreads();
-    }
-    if (tid == 0) a.cnt_out[q * a.P + p] = cnt < a.kappa ? cnt : a.kappa;
-  }
+  if (lane == 0) seed[q] = fmaxf(seed[q], tau);
 }
 
 // ---------------------------------------------------------------------------- merge
@@ -407,89 +221,62 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ in, 
   }
 }
 
-// choose the launch shape of S2/S3 for a scan over `rows` rows
-struct Shape {
-  bool shared;
-  int nb;
-  int P;
-};
-
-Shape choose_shape(int fmt, int64_t m, int64_t rows, int C) {
+Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C) {
   Shape sh;
   const int qpw_override = tuned_qpw();
-  const int p_override = tuned_splits();
   if (qpw_override > 0) {
     sh.nb = std::max(1, std::min(4, qpw_override / 32));
     sh.shared = m <= sh.nb * 32;
   } else if (m <= 32) {
-    sh = {true, 1, 0};
+    sh.shared = true; sh.nb = 1;
   } else if (m <= 64) {
-    sh = {true, 2, 0};
+    sh.shared = true; sh.nb = 2;
   } else {
-    sh = {false, 4, 0};
+    sh.shared = false; sh.nb = 4;
   }
+  if (sh.shared && sh.nb > 2) sh.nb = 2;
+  if (!sh.shared && sh.nb < 2) sh.nb = 2;
   if (fmt == GV_FP32) sh.nb = 1;
-  if (sh.shared && sh.nb == 4) sh.nb = 2;
-  const int qwg = sh.shared ? 32 * sh.nb : 128 * sh.nb;
-  const int64_t nqb = (m + qwg - 1) / qwg;
-  const int rpi = sh.shared ? 128 : 32;
-  const int64_t ntiles = rows / rpi + C;
-  int P;
-  if (p_override > 0) {
-    P = p_override;
+  if (dp > 160 && sh.nb > 2) sh.nb = 2;  // keeps the query views of the longest rows in registers
+  sh.nqb = (m + 32 * sh.nb - 1) / (32 * sh.nb);
+  const int64_t ntiles = rows / kRows + C;
+  // about 1024 wavefronts (four per compute unit), at least 4 tiles per range
+  int64_t R = tuned_splits() > 0 ? tuned_splits() : std::max<int64_t>(1, 1024 / sh.nqb);
+  R = std::min<int64_t>(R, std::max<int64_t>(1, ntiles / 4));
+  R = std::min<int64_t>(R, 4096);
+  if (sh.shared) {
+    R = (R + 3) / 4 * 4;
+    sh.grid = (int)(sh.nqb * (R / 4));
+    sh.xcd_map = 0;
   } else {
-    // about 512 workgroups in flight, at least 8 tiles per split
-    int64_t want = std::max<int64_t>(8, (512 + nqb - 1) / nqb);
-    P = (int)std::min<int64_t>(want, std::max<int64_t>(1, ntiles / 8));
-    P = std::min(P, 1024);
+    const int64_t qgroups = (sh.nqb + 3) / 4;
+    if (qgroups > 1 && R >= 8) R = R / 8 * 8;
+    sh.xcd_map = (qgroups > 1 && R % 8 == 0) ? 1 : 0;
+    sh.grid = (int)(qgroups * R);
   }
-  if (nqb > 1 && P >= 8) P = P / 8 * 8;
-  sh.P = std::max(1, P);
+  sh.R = (int)R;
   return sh;
 }
 
-template <int FMT, int KSM>
-gv_status launch_score(const Shape& sh, const ScoreArgs& args, hipStream_t st, unsigned grid) {
-  if constexpr (FMT == GV_FP32) {
-    if (sh.shared)
-      hipLaunchKernelGGL((k_score_select<FMT, KSM, 1, true>), dim3(grid), dim3(256), 0, st, args);
-    else
-      hipLaunchKernelGGL((k_score_select<FMT, KSM, 1, false>), dim3(grid), dim3(256), 0, st, args);
-  } else {
-    if (sh.shared && sh.nb == 1)
-      hipLaunchKernelGGL((k_score_select<FMT, KSM, 1, true>), dim3(grid), dim3(256), 0, st, args);
-    else if (sh.shared)
-      hipLaunchKernelGGL((k_score_select<FMT, KSM, 2, true>), dim3(grid), dim3(256), 0, st, args);
-    else
-      hipLaunchKernelGGL((k_score_select<FMT, KSM, 4, false>), dim3(grid), dim3(256), 0, st, args);
+
+template <int MODE>
+gv_status dispatch_fmt(int fmt, int dp, const Shape& sh, const ScoreArgs& args, hipStream_t st) {
+  switch (fmt) {
+    case GV_FP32: return dispatch_scan<GV_FP32, MODE>(dp, sh, args, st);
+    case GV_FP16: return dispatch_scan<GV_FP16, MODE>(dp, sh, args, st);
+    case GV_BF16: return dispatch_scan<GV_BF16, MODE>(dp, sh, args, st);
+    default: return dispatch_scan<GV_FP8_E4M3, MODE>(dp, sh, args, st);
   }
-  GV_HIP(hipGetLastError());
-  return GV_OK;
 }
 
-template <int FMT>
-gv_status dispatch_ks(int ks, const Shape& sh, const ScoreArgs& args, hipStream_t st, unsigned grid) {
-  if constexpr (FMT == GV_FP32) {
-    if (ks <= 32) return launch_score<FMT, 32>(sh, args, st, grid);
-    if (ks <= 64) return launch_score<FMT, 64>(sh, args, st, grid);
-    if (ks <= 80) return launch_score<FMT, 80>(sh, args, st, grid);
-    if (ks <= 128) return launch_score<FMT, 128>(sh, args, st, grid);
-  } else {
-    if (ks <= 4) return launch_score<FMT, 4>(sh, args, st, grid);
-    if (ks <= 8) return launch_score<FMT, 8>(sh, args, st, grid);
-    if (ks <= 10) return launch_score<FMT, 10>(sh, args, st, grid);
-    if (ks <= 16) return launch_score<FMT, 16>(sh, args, st, grid);
-  }
-  set_error("reduced dimension above 256 is not supported by the scoring kernel");
-  return GV_EUNSUPPORTED;
-}
-
-// sampling strides of the threshold cascade, coarsest first, ending with 1
-std::vector<int> cascade(int64_t m, int64_t n, int kappa) {
-  std::vector<int> s{1};
-  if (m < 8) return s;
-  const int64_t min_rows = 64LL * kappa;
-  for (int64_t stride = 16; n / stride >= min_rows && stride <= 4096; stride *= 16) s.insert(s.begin(), (int)stride);
+// Sampling strides of the threshold cascade, sparsest first: the sparsest
+// sample (dense scan) holds at least 8 * kappa rows; each next level is 16 times
+// denser; the last entry, 1, is the full scan.  Small databases get no cascade.
+std::vector<int64_t> cascade(int64_t n, int kappa) {
+  std::vector<int64_t> s{1};
+  int64_t top = 0;
+  for (int64_t stride = 16; n / stride >= 8LL * kappa && stride <= (1LL << 24); stride *= 16) top = stride;
+  for (int64_t stride = 16; stride <= top; stride *= 16) s.insert(s.begin(), stride);
   return s;
 }
 
@@ -499,91 +286,140 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
                           int32_t* cand_ids, float* cand_scores, hipStream_t st) {
   if (m == 0) return GV_OK;
   const int fmt = idx->fmt;
-  const int km = (fmt == GV_FP32) ? 2 : 16;
-  const std::vector<int> levels = cascade(m, idx->n, kappa);
+  const int cap = tuned_cap() > 0 ? tuned_cap() : kCap;
+  if (cap < kappa + kRows + 1) {
+    set_error("candidate cap must exceed kappa + 32");
+    return GV_EINVAL;
+  }
+  const std::vector<int64_t> levels = cascade(idx->n, kappa);
+  const int64_t ntiles = idx->n_pad / kRows;
 
-  // one scratch allocation sized for the largest level
-  int Pmax = 1;
-  for (int s : levels) Pmax = std::max(Pmax, choose_shape(fmt, m, idx->n / s, idx->C).P);
-  const int64_t nl_max = m * Pmax;
+  // launch shapes per level
+  std::vector<Shape> shapes;
+  int Rmax = 1;
+  for (size_t li = 0; li < levels.size(); ++li) {
+    const int64_t s = levels[li];
+    Shape sh = choose_shape(fmt, idx->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
+    if (li > 0 && s > 1) {
+      // pilot: ranges of at least 16 sampled tiles, at most 64 per query block
+      int64_t R = std::max<int64_t>(1, std::min<int64_t>(64, (ntiles + s - 1) / s / 16));
+      if (sh.shared) R = (R + 3) / 4 * 4;
+      else if (R >= 8) R = R / 8 * 8;
+      sh.R = (int)R;
+      const int64_t qgroups = (sh.nqb + 3) / 4;
+      sh.xcd_map = (!sh.shared && qgroups > 1 && R % 8 == 0) ? 1 : 0;
+      sh.grid = (int)(sh.shared ? sh.nqb * (R / 4) : qgroups * R);
+    } else if (li == 0 && s > 1) {
+      sh.R = sh.shared ? 4 : 1;  // dense scan of a small sample
+      sh.xcd_map = 0;
+      sh.grid = (int)(sh.shared ? sh.nqb : (sh.nqb + 3) / 4);
+    }
+    shapes.push_back(sh);
+    // every level except a dense sample scan writes m x R candidate lists
+    const bool dense_level = levels.size() > 1 && li == 0;
+    if (!dense_level) Rmax = std::max(Rmax, sh.R);
+  }
+  const int64_t nl_max = m * Rmax;
+  const int64_t ns = levels.size() > 1 ? ((ntiles + levels[0] - 1) / levels[0]) * kRows : 0;
+
   uint64_t* buf = nullptr;
   int32_t* cnt = nullptr;
-  float* tau[2] = {nullptr, nullptr};
+  float* seed = nullptr;
+  uint32_t* tau_ord = nullptr;
+  int32_t* kcount = nullptr;
+  float* dense = nullptr;
   uint64_t* lv_keys[2] = {nullptr, nullptr};
   int32_t* lv_cnt[2] = {nullptr, nullptr};
-  GV_HIP(hipMallocAsync((void**)&buf, sizeof(uint64_t) * nl_max * kCap, st));
-  GV_HIP(hipMallocAsync((void**)&cnt, sizeof(int32_t) * nl_max, st));
   gv_status s = GV_OK;
-  if (levels.size() > 1) {
-    if (hipMallocAsync((void**)&tau[0], sizeof(float) * m, st) != hipSuccess ||
-        hipMallocAsync((void**)&tau[1], sizeof(float) * m, st) != hipSuccess)
+  auto alloc = [&](void** p, size_t bytes) {
+    if (s == GV_OK && hipMallocAsync(p, std::max<size_t>(bytes, 8), st) != hipSuccess) {
+      set_error("search scratch allocation failed");
       s = GV_ENOMEM;
+    }
+  };
+  alloc((void**)&buf, sizeof(uint64_t) * nl_max * kCap);
+  alloc((void**)&cnt, sizeof(int32_t) * nl_max);
+  if (levels.size() > 1) {
+    alloc((void**)&seed, sizeof(float) * m);
+    alloc((void**)&tau_ord, sizeof(uint32_t) * m);
+    alloc((void**)&kcount, sizeof(int32_t) * m);
+    alloc((void**)&dense, sizeof(float) * m * ns);
   }
-  const int Lo_max = (Pmax + kMergeG - 1) / kMergeG;
-  if (s == GV_OK && Lo_max > 1) {
-    for (int i = 0; i < 2; ++i)
-      if (hipMallocAsync((void**)&lv_keys[i], sizeof(uint64_t) * m * Lo_max * kappa, st) != hipSuccess ||
-          hipMallocAsync((void**)&lv_cnt[i], sizeof(int32_t) * m * Lo_max, st) != hipSuccess)
-        s = GV_ENOMEM;
-  }
+  const int Lo_max = (shapes.back().R + kMergeG - 1) / kMergeG;
+  if (Lo_max > 1)
+    for (int i = 0; i < 2; ++i) {
+      alloc((void**)&lv_keys[i], sizeof(uint64_t) * m * Lo_max * kappa);
+      alloc((void**)&lv_cnt[i], sizeof(int32_t) * m * Lo_max);
+    }
 
-  const float* tau_in = nullptr;
+  ScoreArgs args{};
+  args.xlow = (const uint8_t*)idx->xlow;
+  args.ids = idx->ids;
+  args.scale = idx->scale;
+  args.offsets = idx->offsets;
+  args.qhat = (const uint8_t*)qhat;
+  args.qscale = t;
+  args.buf = buf;
+  args.cnt_out = cnt;
+  args.tau_ord = tau_ord;
+  args.kcount = kcount;
+  args.dense = dense;
+  args.m = m;
+  args.n_pad = idx->n_pad;
+  args.C = idx->C;
+  args.dp = idx->dp;
+
+  const unsigned qgrid = (unsigned)((m + 255) / 256);
+  if (s == GV_OK && levels.size() > 1)
+    hipLaunchKernelGGL(k_seed_init, dim3(qgrid), dim3(256), 0, st, m, seed, tau_ord, kcount);
   for (size_t li = 0; li < levels.size() && s == GV_OK; ++li) {
-    const int stride = levels[li];
+    const Shape& sh = shapes[li];
     const bool last = li + 1 == levels.size();
-    const Shape sh = choose_shape(fmt, m, idx->n / stride, idx->C);
-    const int qwg = sh.shared ? 32 * sh.nb : 128 * sh.nb;
-    const int64_t nqb = (m + qwg - 1) / qwg;
-    const int P = sh.P;
-    ScoreArgs args;
-    args.xlow = (const uint8_t*)idx->xlow;
-    args.ids = idx->ids;
-    args.scale = idx->scale;
-    args.offsets = idx->offsets;
-    args.qhat = (const uint8_t*)qhat;
-    args.qscale = t;
-    args.tau_init = tau_in;
-    args.buf = buf;
-    args.cnt_out = cnt;
-    args.m = m;
-    args.C = idx->C;
-    args.dp = idx->dp;
-    args.ks = idx->dp / km;
-    args.kappa = kappa;
-    args.P = P;
-    args.nqb = (int)nqb;
-    args.stride = stride;
-    args.xcd_map = (nqb > 1 && P % 8 == 0) ? 1 : 0;
-    const int64_t grid64 = nqb * P;
-    if (grid64 > 0x7fffffff) {
-      s = GV_EUNSUPPORTED;
+    const bool dense_level = levels.size() > 1 && li == 0;
+    if (!dense_level && (int64_t)sh.R > Rmax) {  // scratch must cover every list the launch writes
+      set_error("internal: candidate scratch smaller than the launch");
+      s = GV_EDEVICE;
       break;
     }
-    const unsigned grid = (unsigned)grid64;
-    if (last) profile_mark(st, 0, true);
-    switch (fmt) {
-      case GV_FP32: s = dispatch_ks<GV_FP32>(args.ks, sh, args, st, grid); break;
-      case GV_FP16: s = dispatch_ks<GV_FP16>(args.ks, sh, args, st, grid); break;
-      case GV_BF16: s = dispatch_ks<GV_BF16>(args.ks, sh, args, st, grid); break;
-      default: s = dispatch_ks<GV_FP8_E4M3>(args.ks, sh, args, st, grid); break;
+    args.seed = li == 0 ? nullptr : seed;
+    args.R = sh.R;
+    args.nqb = (int)sh.nqb;
+    args.stride = (int)levels[li];
+    args.xcd_map = sh.xcd_map;
+    if (last) {
+      args.kappa = kappa;
+      args.cap = cap;
+      profile_mark(st, 0, true);
+      s = dispatch_fmt<kMain>(fmt, idx->dp, sh, args, st);
+      profile_mark(st, 0, false);
+    } else if (li == 0) {
+      args.kappa = kappa;
+      args.cap = cap;
+      s = dispatch_fmt<kDense>(fmt, idx->dp, sh, args, st);
+      if (s == GV_OK)
+        hipLaunchKernelGGL(k_dense_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, dense, m, ns, kappa, seed);
+    } else {
+      const int kr = (kappa + sh.R - 1) / sh.R;
+      args.kappa = kr;
+      args.cap = std::max(128, (kr + kRows + 1 + 31) / 32 * 32);
+      s = dispatch_fmt<kPilot>(fmt, idx->dp, sh, args, st);
+      if (s == GV_OK) hipLaunchKernelGGL(k_seed_update, dim3(qgrid), dim3(256), 0, st, m, kappa, seed, tau_ord, kcount);
     }
-    if (last) profile_mark(st, 0, false);
-    if (s != GV_OK) break;
+  }
 
-    // tree merge of the m x P partial lists
-    float* tau_out = last ? nullptr : tau[li & 1];
+  // tree merge of the m x R partial lists of the full scan
+  if (s == GV_OK) {
     const uint64_t* in = buf;
     const int32_t* in_cnt = cnt;
     int64_t in_stride = kCap;
-    int L = P;
+    int L = shapes.back().R;
     int which = 0;
-    if (last) profile_mark(st, 1, true);
+    profile_mark(st, 1, true);
     while (true) {
       const int Lo = (L + kMergeG - 1) / kMergeG;
       if (Lo == 1) {
         hipLaunchKernelGGL(k_merge, dim3((unsigned)m), dim3(256), 0, st, in, in_cnt, in_stride, L, kappa,
-                           (uint64_t*)nullptr, (int32_t*)nullptr, 1, last ? cand_ids : (int32_t*)nullptr,
-                           last ? cand_scores : (float*)nullptr, tau_out);
+                           (uint64_t*)nullptr, (int32_t*)nullptr, 1, cand_ids, cand_scores, (float*)nullptr);
         break;
       }
       hipLaunchKernelGGL(k_merge, dim3((unsigned)(m * Lo)), dim3(256), 0, st, in, in_cnt, in_stride, L, kappa,
@@ -594,16 +430,11 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
       L = Lo;
       which ^= 1;
     }
-    if (last) profile_mark(st, 1, false);
-    tau_in = tau_out;
+    profile_mark(st, 1, false);
   }
-  for (int i = 0; i < 2; ++i) {
-    if (lv_keys[i]) (void)hipFreeAsync(lv_keys[i], st);
-    if (lv_cnt[i]) (void)hipFreeAsync(lv_cnt[i], st);
-    if (tau[i]) (void)hipFreeAsync(tau[i], st);
-  }
-  GV_HIP(hipFreeAsync(buf, st));
-  GV_HIP(hipFreeAsync(cnt, st));
+  for (void* p : {(void*)buf, (void*)cnt, (void*)seed, (void*)tau_ord, (void*)kcount, (void*)dense,
+                  (void*)lv_keys[0], (void*)lv_keys[1], (void*)lv_cnt[0], (void*)lv_cnt[1]})
+    if (p) (void)hipFreeAsync(p, st);
   GV_TRY(s);
   GV_HIP(hipGetLastError());
   return GV_OK;
@@ -612,53 +443,76 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
 // ============================================================================ S4
 namespace {
 
-__global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Q,
-                                                const int32_t* __restrict__ cand, int kappa, int k,
-                                                int32_t* __restrict__ out_ids, float* __restrict__ out_scores) {
+// One workgroup per query, sixteen wavefronts; each wavefront scores four
+// candidate rows at a time so their loads are in flight together.
+constexpr int kRerankThreads = 1024;
+
+__global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restrict__ X, int64_t n, int D,
+                                                           const float* __restrict__ Q,
+                                                           const int32_t* __restrict__ cand, int kappa, int k,
+                                                           int32_t* __restrict__ out_ids,
+                                                           float* __restrict__ out_scores) {
   __shared__ double s_score[256];
   __shared__ int32_t s_id[256];
+  constexpr int W = kRerankThreads / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t q = blockIdx.x;
   const float* qv = Q + q * D;
-  for (int i = tid; i < 256; i += 256) {
-    s_score[i] = -INFINITY;
-    s_id[i] = 0x7fffffff;
+  if (tid < 256) {
+    s_score[tid] = -INFINITY;
+    s_id[tid] = 0x7fffffff;
   }
   __syncthreads();
   // exact <q, x> with FP64 accumulation of exact FP32 x FP32 products
-  for (int ci = wave; ci < kappa; ci += 4) {
-    const int32_t id = cand[q * kappa + ci];
-    if (id < 0 || id >= n) continue;  // missing candidate (e.g. non-finite query scores)
-    const float* x = X + (int64_t)id * D;
-    double s = 0.0;
-    for (int j = lane; j < D; j += 64) s += (double)x[j] * (double)qv[j];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) {
-      s_score[ci] = s;
-      s_id[ci] = id;
+  for (int c0 = wave * 4; c0 < kappa; c0 += W * 4) {
+    int32_t id[4];
+    bool ok[4];
+    const float* x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      id[u] = (c0 + u < kappa) ? cand[q * kappa + c0 + u] : -1;
+      ok[u] = id[u] >= 0 && id[u] < n;  // a missing candidate (non-finite query scores) is skipped
+      x[u] = X + (ok[u] ? (int64_t)id[u] : 0) * D;
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = lane; j < D; j += 64) {
+      const double qj = (double)qv[j];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += (double)x[u][j] * qj;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double v = acc[u];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0 && ok[u]) {
+        s_score[c0 + u] = v;
+        s_id[c0 + u] = id[u];
+      }
     }
   }
   __syncthreads();
   // bitonic sort of 256 (score, id) pairs: score desc, then id asc
   for (int size = 2; size <= 256; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const int i = tid, j = i ^ stride;
-      if (j > i) {
-        const bool desc = (i & size) == 0;
-        const double xs = s_score[i], ys = s_score[j];
-        const int32_t xi = s_id[i], yi = s_id[j];
-        const bool x_better = (xs > ys) || (xs == ys && xi < yi);
-        if (desc ? !x_better : x_better) {
-          s_score[i] = ys;
-          s_score[j] = xs;
-          s_id[i] = yi;
-          s_id[j] = xi;
+      if (tid < 256) {
+        const int i = tid, j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          const double xs = s_score[i], ys = s_score[j];
+          const int32_t xi = s_id[i], yi = s_id[j];
+          const bool x_better = (xs > ys) || (xs == ys && xi < yi);
+          if (desc ? !x_better : x_better) {
+            s_score[i] = ys;
+            s_score[j] = xs;
+            s_id[i] = yi;
+            s_id[j] = xi;
+          }
         }
       }
       __syncthreads();
     }
   }
-  for (int i = tid; i < k; i += 256) {
+  for (int i = tid; i < k; i += kRerankThreads) {
     out_ids[q * k + i] = s_id[i];
     if (out_scores) out_scores[q * k + i] = (float)s_score[i];
   }
@@ -669,7 +523,7 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ X, int
 gv_status rerank_impl(const gv_index* idx, const float* Q, int64_t m, const int32_t* cand, int kappa, int k,
                       int32_t* out_ids, float* out_scores, hipStream_t st) {
   if (m == 0) return GV_OK;
-  hipLaunchKernelGGL(k_rerank, dim3((unsigned)m), dim3(256), 0, st, idx->X, idx->n, idx->D, Q, cand, kappa, k, out_ids,
+  hipLaunchKernelGGL(k_rerank, dim3((unsigned)m), dim3(kRerankThreads), 0, st, idx->X, idx->n, idx->D, Q, cand, kappa, k, out_ids,
                      out_scores);
   GV_HIP(hipGetLastError());
   return GV_OK;

@@ -40,6 +40,8 @@ CASES = {
     "d16-C4": (101, 64, 4, 20_000, 2_000, 16, 4, 37, 50),
     "d40-C8": (102, 128, 8, 30_000, 3_000, 40, 8, 70, 100),
     "d160-C8": (103, 256, 8, 24_000, 4_000, 160, 8, 65, 200),
+    # large enough for the threshold cascade: dense sample, pilot scan, full scan
+    "n300k": (106, 64, 4, 300_000, 2_000, 32, 4, 40, 50),
 }
 
 
@@ -149,9 +151,10 @@ def test_encode_matches_oracle(gv, case, fmt):
 # ----------------------------------------------------------------------------- S1
 
 @pytest.mark.parametrize("fmt", ["fp32", "fp16", "bf16", "fp8"])
-def test_project_matches_oracle(gv, fmt):
-    cfg, D, J, n, ml, d, C, m, kappa = CASES["d40-C8"]
-    _say(f"[project] {fmt}")
+@pytest.mark.parametrize("m", [5, 70])
+def test_project_matches_oracle(gv, fmt, m):
+    cfg, D, J, n, ml, d, C, _, kappa = CASES["d40-C8"]
+    _say(f"[project] {fmt} m{m}")
     X, QL, Q = problem(cfg, D, J, n, ml, m)
     om = oracle_model(cfg, D, J, n, ml, d, C, 7)
     model = gv.model_import(om.mu, om.A, om.B)
@@ -185,6 +188,9 @@ REGIMES = [
     ("d40-C8", 70, "m70"),
     ("d160-C8", 65, "m65"),
     ("d160-C8", 600, "m600"),
+    ("n300k", 1, "m1"),
+    ("n300k", 40, "m40"),
+    ("n300k", 130, "m130"),
 ]
 
 
@@ -331,3 +337,30 @@ def test_deterministic_repeat(gv):
         gv.search_tuning(0, 0)
     torch.cuda.synchronize()
     assert torch.equal(c1, c2) and torch.equal(d1, d2)
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "fp8"])
+@pytest.mark.parametrize("m", [20, 65])
+def test_compaction_path(gv, fmt, m):
+    """Few row ranges and a small candidate cap force many in-loop compactions
+    (wavefront radix select + threshold raise); the result must not change."""
+    _say(f"[compaction] {fmt} m{m}")
+    X, Q, om, oi, model, idx, Xd, kappa = _search_setup(gv, "d160-C8", fmt, m)
+    Qd = dev(Q)
+    _, t, qhat = gv.project(model, fmt, Qd, want_qc=False)
+    c1, d1 = gv.score_topk(idx, qhat, t, kappa)
+    gv.search_tuning(splits=4, qpw=0, cap=512)
+    try:
+        c2, d2 = gv.score_topk(idx, qhat, t, kappa)
+    finally:
+        gv.search_tuning(0, 0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(c1, c2) and torch.equal(d1, d2)
+    out = G.search(oi, om.A, Q, 10, kappa)
+    tol = reduced_score_tolerance(out, oi, idx.d_pad)
+    n = X.shape[0]
+    c2 = c2.cpu().numpy(); d2 = d2.cpu().numpy()
+    for qi in range(m):
+        by_id = np.empty(n); by_id[oi.ids] = out["scores"][qi]
+        tol_id = np.empty(n); tol_id[oi.ids] = tol[qi]
+        check_topk_sets(c2[qi], d2[qi], by_id, tol_id, kappa, f"q{qi}")

@@ -87,7 +87,15 @@ def test_host_argument_errors():
     assert lib.gv_search(None, None, None, 1, 10, 20, None, None, None) == -4
     assert lib.gv_model_stats(None, None, None, None, None, None, None, None) == -4
     assert lib.gv_host_eigh(0, None, None, None) == -1
-    assert lib.gv_search_tuning(0, 48) == -1
-    assert lib.gv_search_tuning(0, 0) == 0
+    assert lib.gv_search_tuning(0, 48, 0) == -1
+    assert lib.gv_search_tuning(0, 0, 100) == -1
+    assert lib.gv_search_tuning(5000, 0, 0) == -1
+    assert lib.gv_search_tuning(0, 0, 0) == 0
     lib.gv_model_destroy(None)
     lib.gv_index_destroy(None)
+
+
+def test_padded_dim():
+    import paper_2410_22347_amd as gv
+    assert [gv.padded_dim(d) for d in (0, 1, 16, 32, 33, 64, 100, 128, 129, 160, 161, 192, 200, 256)] == \
+        [0, 32, 32, 32, 64, 64, 128, 128, 160, 160, 192, 192, 256, 256]
