@@ -241,8 +241,9 @@ gv_status gv_rerank(const gv_index* index, const float* Q, int64_t m, const int3
  * gv_search_tuning -- override the launch shape of S2/S3 for the calling
  * thread's following searches (0 restores the automatic choice):
  * splits = row ranges per query block (1..4096), qpw = queries per wavefront
- * (32, 64 or 128), cap = candidate slots per (query, row range) before a
- * compaction to the kappa best (512..2048, must exceed kappa + 32).  Results
+ * (32, 64 or 128), cap = key slots per (query, row range) list; a list is
+ * compacted to its kappa best when it may overflow before the next check
+ * (512..2048; a search with cap < kappa + 417 fails with GV_EINVAL).  Results
  * do not depend on these; only speed does.  Errors: GV_EINVAL.
  */
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap);

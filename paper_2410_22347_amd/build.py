@@ -22,6 +22,10 @@ ARCH = os.environ.get("GV_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # matrix-core results in ordinary VGPRs: the filters read them with
+             # vector ALU ops, and accumulation-register copies would otherwise
+             # force waits on the tile loads in flight
+             "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v3"]
 

@@ -274,6 +274,7 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
     x->n = n;
     x->tags = nullptr;
     x->offsets = nullptr;
+    x->seg_end = nullptr;
     x->ids = nullptr;
     x->xlow = nullptr;
     x->scale = nullptr;
@@ -285,6 +286,7 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
     };
     x->n_pad = 0;
     if (hipMalloc(&x->tags, n) != hipSuccess || hipMalloc(&x->offsets, sizeof(int64_t) * (x->C + 1)) != hipSuccess ||
+        hipMalloc(&x->seg_end, sizeof(int64_t) * x->C) != hipSuccess ||
         hipMalloc(&x->scale, sizeof(float) * x->C) != hipSuccess) {
       set_error("gv_encode: device allocation failed");
       return fail(GV_ENOMEM);
@@ -353,6 +355,7 @@ void gv_index_destroy(gv_index* x) {
   x->magic = 0;
   if (x->tags) (void)hipFree(x->tags);
   if (x->offsets) (void)hipFree(x->offsets);
+  if (x->seg_end) (void)hipFree(x->seg_end);
   if (x->ids) (void)hipFree(x->ids);
   if (x->xlow) (void)hipFree(x->xlow);
   if (x->scale) (void)hipFree(x->scale);

@@ -184,6 +184,7 @@ struct gv_index {
   int device;
   uint8_t* tags;     // device n, cluster of each original row
   int64_t* offsets;  // device C+1, padded segment starts (multiples of 32)
+  int64_t* seg_end;  // device C, first padding row of each segment (offsets[c] + rows of c)
   int32_t* ids;      // device n_pad, original id of each stored row, -1 for padding
   void* xlow;        // device n_pad x dp elements of fmt, matrix-core tiled
   float* scale;      // device C

@@ -5,6 +5,7 @@
 //   tags[n]            uint8, cluster of each original row;
 //   offsets[C+1]       int64, start of each cluster's stored segment; segments
 //                      are padded to a multiple of 32 rows (one tile);
+//   seg_end[C]         int64, first padding row of each segment;
 //   ids[n_pad]         int32, original row id of each stored row (stable:
 //                      increasing inside a segment), -1 for padding rows;
 //   xlow[n_pad][d_pad] storage format, zero padded, in matrix-core operand
@@ -176,11 +177,15 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
     GV_HIP(hipMemsetAsync(idx->ids, 0xFF, sizeof(int32_t) * run, st));  // -1: padding
     GV_HIP(hipMemcpyAsync(base, h_base.data(), sizeof(int64_t) * nb * C, hipMemcpyHostToDevice, st));
     GV_HIP(hipMemcpyAsync(idx->offsets, idx->h_offsets.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, st));
+    std::vector<int64_t> h_end(C);
+    for (int c = 0; c < C; ++c) h_end[c] = idx->h_offsets[c] + idx->h_counts[c];
+    GV_HIP(hipMemcpyAsync(idx->seg_end, h_end.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nb), dim3(64), 0, st, idx->tags, n, C, base, nb, idx->ids,
                        ids64);
     GV_HIP(hipGetLastError());
     GV_HIP(hipFreeAsync(hist, st));
     GV_HIP(hipFreeAsync(base, st));
+    GV_HIP(hipStreamSynchronize(st));  // the host staging vectors end with this block
   }
   const int64_t n_pad = idx->n_pad;
 

@@ -8,8 +8,7 @@ gv_status dispatch_scan(int dp, const scan::Shape& sh, const scan::ScoreArgs& ar
   return scan::dispatch_ks<FMT, MODE>(dp, sh, args, st);
 }
 
-template gv_status dispatch_scan<GV_BF16, scan::kMain>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
-template gv_status dispatch_scan<GV_BF16, scan::kPilot>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
+template gv_status dispatch_scan<GV_BF16, scan::kFilter>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
 template gv_status dispatch_scan<GV_BF16, scan::kDense>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
 
 }  // namespace gv

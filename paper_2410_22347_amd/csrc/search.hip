@@ -100,24 +100,10 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
 namespace {
 using namespace scan;
 
-// seed[q] = -inf, tau_ord[q] = max, kcount[q] = 0
-__global__ void k_seed_init(int64_t m, float* __restrict__ seed, uint32_t* __restrict__ tau_ord,
-                            int32_t* __restrict__ kcount) {
+// seed[q] = -inf
+__global__ void k_seed_init(int64_t m, float* __restrict__ seed) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  seed[q] = -INFINITY;
-  tau_ord[q] = 0xFFFFFFFFu;
-  kcount[q] = 0;
-}
-
-// after a pilot scan: raise the seed when the ranges kept kappa keys in total
-__global__ void k_seed_update(int64_t m, int kappa, float* __restrict__ seed, uint32_t* __restrict__ tau_ord,
-                              int32_t* __restrict__ kcount) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= m) return;
-  if (kcount[q] >= kappa) seed[q] = fmaxf(seed[q], unorder_f32(tau_ord[q]));
-  tau_ord[q] = 0xFFFFFFFFu;
-  kcount[q] = 0;
+  if (q < m) seed[q] = -INFINITY;
 }
 
 // after the dense scan: seed = kappa-th best score of the sample (one wavefront per query)
@@ -139,85 +125,128 @@ __global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ 
   if (lane == 0) seed[q] = fmaxf(seed[q], tau);
 }
 
-// ---------------------------------------------------------------------------- merge
-// Merge groups of G lists per query into one list of the kappa best keys.
-// Final level: either (ids, scores) sorted by key (score desc, id asc), or, for
-// a sampling scan of the cascade, only tau = the kappa-th best score (-inf when
-// fewer than kappa candidates exist).
-constexpr int kMergeG = 16;
+// ---------------------------------------------------------------------------- select
+// Top kappa of the R lists of one query (one workgroup per query).  The lists
+// are streamed through an LDS window: each window is appended to the best
+// kappa so far and cut back to kappa by a radix select.  Keys are ordered by
+// (score desc, stored row asc) in the lists; the final level re-keys them by
+// original id, so ties resolve by (score desc, id asc).
+// FINAL: the kappa best, sorted, as (ids, scores) (-1 / NaN past the end when
+// fewer exist).  Otherwise: seed[q] = max(seed[q], kappa-th best score).
+constexpr int kSelWin = 4096;
+constexpr int kMaxLists = 4096;
 
-__global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ in, const int32_t* __restrict__ in_cnt,
-                                               int64_t in_stride, int L, int kappa, uint64_t* __restrict__ out,
-                                               int32_t* __restrict__ out_cnt, int Lo, int32_t* __restrict__ ids,
-                                               float* __restrict__ scores, float* __restrict__ tau_out) {
-  __shared__ uint64_t keys[kMergeG * 256];
-  __shared__ int32_t s_base[kMergeG + 1];
-  __shared__ uint64_t s_stage[256];
+template <bool FINAL>
+__global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf, const int32_t* __restrict__ cnt,
+                                                int R, int cap, int kappa, const int32_t* __restrict__ ids,
+                                                float* __restrict__ seed, int32_t* __restrict__ out_ids,
+                                                float* __restrict__ out_scores) {
+  __shared__ uint64_t keys[kSelWin];
+  __shared__ int32_t pre[kMaxLists + 1];
+  __shared__ uint64_t stage[256];
+  __shared__ int32_t wsum[4];
   __shared__ uint32_t s_kept;
   __shared__ SelectSmem sel;
-  const int tid = threadIdx.x;
-  const int64_t q = blockIdx.x / Lo;
-  const int g = blockIdx.x % Lo;
-  const int l0 = g * kMergeG, l1 = min(L, l0 + kMergeG);
-  if (tid == 0) {
-    s_base[0] = 0;
-    for (int l = l0; l < l1; ++l) s_base[l - l0 + 1] = s_base[l - l0] + in_cnt[q * L + l];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t q = blockIdx.x;
+  const int32_t* c = cnt + q * R;
+
+  // exclusive prefix of the list lengths
+  const int per = (R + 255) / 256;
+  int local = 0;
+  for (int j = 0; j < per; ++j) {
+    const int L = tid * per + j;
+    if (L < R) local += c[L];
   }
-  __syncthreads();
-  const int total = s_base[l1 - l0];
-  for (int l = l0; l < l1; ++l) {
-    const uint64_t* src = in + (q * L + l) * in_stride;
-    const int b = s_base[l - l0], nl = s_base[l - l0 + 1] - b;
-    for (int i = tid; i < nl; i += 256) keys[b + i] = src[i];
+  int incl = local;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
   }
+  if (lane == 63) wsum[wave] = incl;
   __syncthreads();
-  if (tau_out) {  // sampling scan: only the kappa-th best score matters
-    float tau = -INFINITY;
-    if (total >= kappa) tau = key_score(block_kth(keys, total, kappa, sel));
-    if (tid == 0) tau_out[q] = tau;
+  int run = incl - local;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+  for (int j = 0; j < per; ++j) {
+    const int L = tid * per + j;
+    if (L < R) {
+      pre[L] = run;
+      run += c[L];
+    }
+  }
+  const int64_t total = (int64_t)wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  if (tid == 0) pre[R] = (int32_t)total;
+  __syncthreads();
+
+  int kept = 0;
+  for (int64_t w0 = 0; w0 < total; w0 += kSelWin - kappa) {
+    const int wn = (int)std::min<int64_t>(total - w0, kSelWin - kappa);
+    for (int f = tid; f < wn; f += 256) {
+      const int g = (int)(w0 + f);
+      int lo = 0, hi = R - 1;  // list holding flat index g: last L with pre[L] <= g
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+      }
+      uint64_t k = buf[(q * R + lo) * (int64_t)cap + (g - pre[lo])];
+      if (FINAL) {
+        const uint32_t row = 0xFFFFFFFFu - (uint32_t)k;
+        k = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - (uint32_t)ids[row]);
+      }
+      keys[kept + f] = k;
+    }
+    __syncthreads();
+    const int n = kept + wn;
+    if (n > kappa) {
+      const uint64_t kth = block_kth(keys, n, kappa, sel);
+      if (tid == 0) s_kept = 0;
+      __syncthreads();
+      for (int i = tid; i < n; i += 256)
+        if (keys[i] >= kth) stage[atomicAdd(&s_kept, 1u)] = keys[i];
+      __syncthreads();
+      for (int i = tid; i < kappa; i += 256) keys[i] = stage[i];
+      __syncthreads();
+      kept = kappa;
+    } else {
+      kept = n;
+    }
+  }
+
+  if (!FINAL) {
+    if (kept < kappa) return;  // fewer than kappa candidates: no bound
+    // the kappa-th best is the smallest kept key
+    uint64_t mn = ~0ull;
+    for (int i = tid; i < kept; i += 256) mn = std::min(mn, keys[i]);
+    for (int o = 32; o > 0; o >>= 1) mn = std::min(mn, (uint64_t)__shfl_xor(mn, o));
+    if (lane == 0) stage[wave] = mn;
+    __syncthreads();
+    if (tid == 0) {
+      const uint64_t m4 = std::min(std::min(stage[0], stage[1]), std::min(stage[2], stage[3]));
+      seed[q] = fmaxf(seed[q], key_score(m4));
+    }
     return;
   }
-  int kept = total;
-  if (total > kappa) {
-    const uint64_t kth = block_kth(keys, total, kappa, sel);
-    if (tid == 0) s_kept = 0;
-    __syncthreads();
-    for (int i = tid; i < total; i += 256)
-      if (keys[i] >= kth) s_stage[atomicAdd(&s_kept, 1u)] = keys[i];
-    __syncthreads();
-    kept = kappa;
-  } else {
-    for (int i = tid; i < total; i += 256) s_stage[i] = keys[i];
-    __syncthreads();
-  }
-  if (!ids) {
-    uint64_t* dst = out + (q * Lo + g) * (int64_t)kappa;
-    for (int i = tid; i < kept; i += 256) dst[i] = s_stage[i];
-    if (tid == 0) out_cnt[q * Lo + g] = kept;
-    return;
-  }
-  // final level: bitonic sort of 256 keys, descending (padding keys are 0)
-  for (int i = tid; i < 256; i += 256)
-    if (i >= kept) s_stage[i] = 0;
+  // bitonic sort of 256 keys, descending (padding keys are 0)
+  stage[tid] = tid < kept ? keys[tid] : 0;
   __syncthreads();
   for (int size = 2; size <= 256; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       const int i = tid, j = i ^ stride;
       if (j > i) {
         const bool desc = (i & size) == 0;
-        uint64_t x = s_stage[i], y = s_stage[j];
+        const uint64_t x = stage[i], y = stage[j];
         if (desc ? (x < y) : (x > y)) {
-          s_stage[i] = y;
-          s_stage[j] = x;
+          stage[i] = y;
+          stage[j] = x;
         }
       }
       __syncthreads();
     }
   }
-  for (int i = tid; i < kappa; i += 256) {
-    const uint64_t k = s_stage[i];
-    ids[q * kappa + i] = (int32_t)key_id(k);
-    scores[q * kappa + i] = key_score(k);
+  if (tid < kappa) {
+    const uint64_t k = stage[tid];
+    out_ids[q * kappa + tid] = (int32_t)key_id(k);
+    out_scores[q * kappa + tid] = key_score(k);
   }
 }
 
@@ -243,7 +272,7 @@ Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C) {
   // about 1024 wavefronts (four per compute unit), at least 4 tiles per range
   int64_t R = tuned_splits() > 0 ? tuned_splits() : std::max<int64_t>(1, 1024 / sh.nqb);
   R = std::min<int64_t>(R, std::max<int64_t>(1, ntiles / 4));
-  R = std::min<int64_t>(R, 4096);
+  R = std::min<int64_t>(R, kMaxLists);
   if (sh.shared) {
     R = (R + 3) / 4 * 4;
     sh.grid = (int)(sh.nqb * (R / 4));
@@ -257,7 +286,6 @@ Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C) {
   sh.R = (int)R;
   return sh;
 }
-
 
 template <int MODE>
 gv_status dispatch_fmt(int fmt, int dp, const Shape& sh, const ScoreArgs& args, hipStream_t st) {
@@ -280,56 +308,58 @@ std::vector<int64_t> cascade(int64_t n, int kappa) {
   return s;
 }
 
+// freed search scratch stays in the stream-ordered pool between calls
+void keep_pool(int dev) {
+  static bool done[64] = {};
+  if (dev < 0 || dev >= 64 || done[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = ~0ull;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  done[dev] = true;
+}
+
 }  // namespace
+
+// smallest list capacity the scan accepts for a given kappa: a list is checked
+// for overflow every 2P + 1 tiles (P <= 6) and takes at most 32 keys per tile
+int min_list_cap(int kappa) { return kappa + kRows * 13 + 1; }
 
 gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t, int64_t m, int kappa,
                           int32_t* cand_ids, float* cand_scores, hipStream_t st) {
   if (m == 0) return GV_OK;
+  keep_pool(idx->device);
   const int fmt = idx->fmt;
   const int cap = tuned_cap() > 0 ? tuned_cap() : kCap;
-  if (cap < kappa + kRows + 1) {
-    set_error("candidate cap must exceed kappa + 32");
+  if (cap < min_list_cap(kappa) || cap > kCap) {
+    set_error("candidate list capacity must lie in [kappa + 417, 2048]");
     return GV_EINVAL;
   }
   const std::vector<int64_t> levels = cascade(idx->n, kappa);
+  const bool has_dense = levels.size() > 1;
   const int64_t ntiles = idx->n_pad / kRows;
 
-  // launch shapes per level
   std::vector<Shape> shapes;
   int Rmax = 1;
   for (size_t li = 0; li < levels.size(); ++li) {
     const int64_t s = levels[li];
     Shape sh = choose_shape(fmt, idx->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
-    if (li > 0 && s > 1) {
-      // pilot: ranges of at least 16 sampled tiles, at most 64 per query block
-      int64_t R = std::max<int64_t>(1, std::min<int64_t>(64, (ntiles + s - 1) / s / 16));
-      if (sh.shared) R = (R + 3) / 4 * 4;
-      else if (R >= 8) R = R / 8 * 8;
-      sh.R = (int)R;
-      const int64_t qgroups = (sh.nqb + 3) / 4;
-      sh.xcd_map = (!sh.shared && qgroups > 1 && R % 8 == 0) ? 1 : 0;
-      sh.grid = (int)(sh.shared ? sh.nqb * (R / 4) : qgroups * R);
-    } else if (li == 0 && s > 1) {
+    if (has_dense && li == 0) {
       sh.R = sh.shared ? 4 : 1;  // dense scan of a small sample
       sh.xcd_map = 0;
       sh.grid = (int)(sh.shared ? sh.nqb : (sh.nqb + 3) / 4);
+    } else {
+      Rmax = std::max(Rmax, sh.R);
     }
     shapes.push_back(sh);
-    // every level except a dense sample scan writes m x R candidate lists
-    const bool dense_level = levels.size() > 1 && li == 0;
-    if (!dense_level) Rmax = std::max(Rmax, sh.R);
   }
-  const int64_t nl_max = m * Rmax;
-  const int64_t ns = levels.size() > 1 ? ((ntiles + levels[0] - 1) / levels[0]) * kRows : 0;
+  const int64_t ns = has_dense ? ((ntiles + levels[0] - 1) / levels[0]) * kRows : 0;
 
   uint64_t* buf = nullptr;
   int32_t* cnt = nullptr;
   float* seed = nullptr;
-  uint32_t* tau_ord = nullptr;
-  int32_t* kcount = nullptr;
   float* dense = nullptr;
-  uint64_t* lv_keys[2] = {nullptr, nullptr};
-  int32_t* lv_cnt[2] = {nullptr, nullptr};
   gv_status s = GV_OK;
   auto alloc = [&](void** p, size_t bytes) {
     if (s == GV_OK && hipMallocAsync(p, std::max<size_t>(bytes, 8), st) != hipSuccess) {
@@ -337,103 +367,67 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
       s = GV_ENOMEM;
     }
   };
-  alloc((void**)&buf, sizeof(uint64_t) * nl_max * kCap);
-  alloc((void**)&cnt, sizeof(int32_t) * nl_max);
-  if (levels.size() > 1) {
+  alloc((void**)&buf, sizeof(uint64_t) * m * Rmax * cap);
+  alloc((void**)&cnt, sizeof(int32_t) * m * Rmax);
+  if (has_dense) {
     alloc((void**)&seed, sizeof(float) * m);
-    alloc((void**)&tau_ord, sizeof(uint32_t) * m);
-    alloc((void**)&kcount, sizeof(int32_t) * m);
     alloc((void**)&dense, sizeof(float) * m * ns);
   }
-  const int Lo_max = (shapes.back().R + kMergeG - 1) / kMergeG;
-  if (Lo_max > 1)
-    for (int i = 0; i < 2; ++i) {
-      alloc((void**)&lv_keys[i], sizeof(uint64_t) * m * Lo_max * kappa);
-      alloc((void**)&lv_cnt[i], sizeof(int32_t) * m * Lo_max);
-    }
 
   ScoreArgs args{};
   args.xlow = (const uint8_t*)idx->xlow;
   args.ids = idx->ids;
   args.scale = idx->scale;
   args.offsets = idx->offsets;
+  args.seg_end = idx->seg_end;
   args.qhat = (const uint8_t*)qhat;
   args.qscale = t;
   args.buf = buf;
   args.cnt_out = cnt;
-  args.tau_ord = tau_ord;
-  args.kcount = kcount;
   args.dense = dense;
   args.m = m;
   args.n_pad = idx->n_pad;
   args.C = idx->C;
   args.dp = idx->dp;
+  args.kappa = kappa;
+  args.cap = cap;
 
-  const unsigned qgrid = (unsigned)((m + 255) / 256);
-  if (s == GV_OK && levels.size() > 1)
-    hipLaunchKernelGGL(k_seed_init, dim3(qgrid), dim3(256), 0, st, m, seed, tau_ord, kcount);
+  if (s == GV_OK && has_dense)
+    hipLaunchKernelGGL(k_seed_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, seed);
   for (size_t li = 0; li < levels.size() && s == GV_OK; ++li) {
     const Shape& sh = shapes[li];
     const bool last = li + 1 == levels.size();
-    const bool dense_level = levels.size() > 1 && li == 0;
-    if (!dense_level && (int64_t)sh.R > Rmax) {  // scratch must cover every list the launch writes
-      set_error("internal: candidate scratch smaller than the launch");
-      s = GV_EDEVICE;
-      break;
-    }
     args.seed = li == 0 ? nullptr : seed;
     args.R = sh.R;
     args.nqb = (int)sh.nqb;
     args.stride = (int)levels[li];
     args.xcd_map = sh.xcd_map;
-    if (last) {
-      args.kappa = kappa;
-      args.cap = cap;
-      profile_mark(st, 0, true);
-      s = dispatch_fmt<kMain>(fmt, idx->dp, sh, args, st);
-      profile_mark(st, 0, false);
-    } else if (li == 0) {
-      args.kappa = kappa;
-      args.cap = cap;
+    if (has_dense && li == 0) {
       s = dispatch_fmt<kDense>(fmt, idx->dp, sh, args, st);
       if (s == GV_OK)
         hipLaunchKernelGGL(k_dense_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, dense, m, ns, kappa, seed);
+      continue;
+    }
+    if (sh.R > Rmax) {  // scratch must cover every list the launch writes
+      set_error("internal: candidate scratch smaller than the launch");
+      s = GV_EDEVICE;
+      break;
+    }
+    if (last) profile_mark(st, 0, true);
+    s = dispatch_fmt<kFilter>(fmt, idx->dp, sh, args, st);
+    if (last) profile_mark(st, 0, false);
+    if (s != GV_OK) break;
+    if (last) {
+      profile_mark(st, 1, true);
+      hipLaunchKernelGGL(k_select<true>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, cap, kappa, idx->ids,
+                         seed, cand_ids, cand_scores);
+      profile_mark(st, 1, false);
     } else {
-      const int kr = (kappa + sh.R - 1) / sh.R;
-      args.kappa = kr;
-      args.cap = std::max(128, (kr + kRows + 1 + 31) / 32 * 32);
-      s = dispatch_fmt<kPilot>(fmt, idx->dp, sh, args, st);
-      if (s == GV_OK) hipLaunchKernelGGL(k_seed_update, dim3(qgrid), dim3(256), 0, st, m, kappa, seed, tau_ord, kcount);
+      hipLaunchKernelGGL(k_select<false>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, cap, kappa, idx->ids,
+                         seed, (int32_t*)nullptr, (float*)nullptr);
     }
   }
-
-  // tree merge of the m x R partial lists of the full scan
-  if (s == GV_OK) {
-    const uint64_t* in = buf;
-    const int32_t* in_cnt = cnt;
-    int64_t in_stride = kCap;
-    int L = shapes.back().R;
-    int which = 0;
-    profile_mark(st, 1, true);
-    while (true) {
-      const int Lo = (L + kMergeG - 1) / kMergeG;
-      if (Lo == 1) {
-        hipLaunchKernelGGL(k_merge, dim3((unsigned)m), dim3(256), 0, st, in, in_cnt, in_stride, L, kappa,
-                           (uint64_t*)nullptr, (int32_t*)nullptr, 1, cand_ids, cand_scores, (float*)nullptr);
-        break;
-      }
-      hipLaunchKernelGGL(k_merge, dim3((unsigned)(m * Lo)), dim3(256), 0, st, in, in_cnt, in_stride, L, kappa,
-                         lv_keys[which], lv_cnt[which], Lo, (int32_t*)nullptr, (float*)nullptr, (float*)nullptr);
-      in = lv_keys[which];
-      in_cnt = lv_cnt[which];
-      in_stride = kappa;
-      L = Lo;
-      which ^= 1;
-    }
-    profile_mark(st, 1, false);
-  }
-  for (void* p : {(void*)buf, (void*)cnt, (void*)seed, (void*)tau_ord, (void*)kcount, (void*)dense,
-                  (void*)lv_keys[0], (void*)lv_keys[1], (void*)lv_cnt[0], (void*)lv_cnt[1]})
+  for (void* p : {(void*)buf, (void*)cnt, (void*)seed, (void*)dense})
     if (p) (void)hipFreeAsync(p, st);
   GV_TRY(s);
   GV_HIP(hipGetLastError());

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "search_common.hpp"
@@ -12,54 +13,51 @@ namespace gv {
 // ============================================================================ S2 + S3
 //
 // Work item = one wavefront = (block of 32*NB queries, one contiguous range of
-// 32-row tiles).  A tile never straddles two clusters, so it meets one eager
-// view q_c per query, held in registers as the matrix-core B operand.  Rows
-// arrive as operand tiles (see tiled_offset): one k-step of a tile is one
-// contiguous block per wavefront, and a ring of three register buffers keeps
-// the next two tiles in flight while the current one is scored.  Scores leave
-// the accumulators only through a threshold filter: a score below the query's
-// current threshold tau can never enter the top kappa, so only survivors are
-// written, as 64-bit keys (score desc, id asc), to the (query, range) buffer.
-// A buffer close to full is compacted by its wavefront to the kappa best keys
-// and tau rises to the kappa-th score.  Wavefronts never wait on each other.
+// 32-row tiles).  A range is walked segment by segment, a segment being the
+// part of the range inside one cluster: the segment's eager views q_c are the
+// matrix-core B operand and stay in registers, the tiles stream through a ring
+// of P register buffers (P-1 tiles in flight while one is scored).  The
+// accumulators are double-buffered so the filter of tile t-1 runs while the
+// matrix core works on tile t.
+//
+// Filter: a score below the query's threshold tau cannot enter the top kappa,
+// so only survivors leave the accumulators, as 64-bit keys (score desc, stored
+// row asc) appended to the (query, range) list.  The two lanes that hold the
+// same query (rows 0-3 and 4-7 of each group of eight) agree on their slots
+// through one cross-half exchange; no atomics.  A list close to full is
+// compacted by its wavefront to its kappa best (ordered by score desc, original
+// id asc) and tau rises to the kappa-th score.  Wavefronts never wait on each
+// other.
 //
 // A workgroup holds four work items: four query blocks on the same rows when
-// queries are many (the rows are fetched once into L1 for all four), or one
+// queries are many (the rows are fetched once into L1/L2 for all four), or one
 // query block on four row ranges when they are few.
 //
-// Threshold cascade (modes): the scan of the whole database (kMain) starts from
-// a per-query seed tau that is a valid lower bound of its kappa-th best score,
-// so only about kappa * 16 scores per query survive.  The seed comes from
-// scans of uniform samples of the tiles (every s-th tile):
-//   kDense  the sparsest sample, every score written out; a selection kernel
-//           takes the kappa-th best per query;
-//   kPilot  denser samples seeded by the previous level; each of R ranges keeps
-//           its ceil(kappa/R) best and publishes how many it kept and the worst
-//           of them: if the ranges kept kappa in total, the minimum of their
-//           worst is a valid seed for the next level.
+// Modes: kFilter as above; kDense writes every score of a (sampled) scan to a
+// dense m x ns matrix (used on the sparsest sample of the threshold cascade).
+// The scan visits every stride-th tile (stride 1: the whole database).
 namespace scan {
 
-constexpr int kCap = 2048;  // candidate slots per (query, range)
+constexpr int kCap = 2048;  // key slots per (query, range) list
 constexpr int kRows = kTileRows;
-enum Mode { kMain = 0, kPilot = 1, kDense = 2 };
+enum Mode { kFilter = 0, kDense = 1 };
 
 struct ScoreArgs {
-  const uint8_t* xlow;    // operand tiles, n_pad x dp elements
-  const int32_t* ids;     // stored row -> original id (-1: padding)
-  const float* scale;     // C
-  const int64_t* offsets; // C + 1 padded segment starts
-  const uint8_t* qhat;    // m x C x dp, storage format
-  const float* qscale;    // m x C
-  const float* seed;      // m seed thresholds, or null (-inf)
-  uint64_t* buf;          // m x R x kCap keys               (kMain, kPilot)
-  int32_t* cnt_out;       // m x R kept per (query, range)   (kMain)
-  uint32_t* tau_ord;      // m: min over ranges, ordered     (kPilot)
-  int32_t* kcount;        // m: kept over ranges             (kPilot)
-  float* dense;           // m x (sampled tiles * 32)        (kDense)
+  const uint8_t* xlow;     // operand tiles, n_pad x dp elements
+  const int32_t* ids;      // stored row -> original id (-1: padding)
+  const float* scale;      // C
+  const int64_t* offsets;  // C + 1 padded segment starts (stored rows)
+  const int64_t* seg_end;  // C: first padding row of each segment
+  const uint8_t* qhat;     // m x C x dp, storage format
+  const float* qscale;     // m x C
+  const float* seed;       // m initial thresholds, or null (-inf)
+  uint64_t* buf;           // kFilter: m x R lists of cap keys
+  int32_t* cnt_out;        // kFilter: m x R list lengths
+  float* dense;            // kDense: m x ns scores (ns = sampled tiles * 32)
   int64_t m, n_pad;
   int C, dp, kappa, R, nqb, cap;
-  int stride;             // scan every stride-th tile
-  int xcd_map;            // 1: workgroups sharing rows are pinned to one XCD
+  int stride;   // scan every stride-th tile
+  int xcd_map;  // 1: workgroups sharing rows are pinned to one XCD
 };
 
 __device__ inline void wave_sync() {
@@ -119,52 +117,100 @@ __device__ uint64_t wave_kth(Load load, int cnt, int kappa, uint32_t* hist) {
 // LDS of one wavefront
 template <int QW>
 struct WaveSmem {
-  int32_t cnt[QW];
   float tau[QW];
   uint32_t hist[256];
-  uint64_t stage[256];
   uint32_t kept;
+  uint64_t idk[kCap];  // compaction: keys ordered by (score desc, id asc)
+  uint32_t row[kCap];  //             and the stored row of each
 };
 
-// Reduce a (query, range) buffer of cnt > keep keys to its `keep` best; returns
-// the smallest kept key.
+// Reduce the list L of n keys (n > keep) to its `keep` best by (score desc,
+// original id asc); the kept keys are rewritten to L[0..keep).  Returns the
+// score of the keep-th best.
 template <int QW>
-__device__ uint64_t wave_compact(uint64_t* qbuf, int cnt, int keep, WaveSmem<QW>& w) {
+__device__ float compact_list(uint64_t* L, int n, int keep, const int32_t* __restrict__ ids, WaveSmem<QW>& w) {
   const int lane = threadIdx.x & 63;
-  // survivors were stored by other lanes of this wavefront: make them visible
-  // and read them coherently from L2
+  // the keys were stored by lanes of this wavefront: make them visible and
+  // read them coherently from L2
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-  auto load = [&](int i) { return __hip_atomic_load(qbuf + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-  const uint64_t kth = wave_kth(load, cnt, keep, w.hist);
-  if (lane == 0) w.kept = 0;
-  wave_sync();
-  for (int i = lane; i < cnt; i += 64) {
-    const uint64_t k = load(i);
-    if (k >= kth) w.stage[atomicAdd(&w.kept, 1u)] = k;
+  for (int i = lane; i < n; i += 64) {
+    const uint64_t k = __hip_atomic_load(L + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t row = 0xFFFFFFFFu - (uint32_t)k;
+    const uint32_t id = (uint32_t)ids[row];
+    w.idk[i] = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - id);
+    w.row[i] = row;
   }
   wave_sync();
-  for (int i = lane; i < keep; i += 64) qbuf[i] = w.stage[i];
+  const uint64_t kth = wave_kth([&](int i) { return w.idk[i]; }, n, keep, w.hist);
+  if (lane == 0) w.kept = 0;
   wave_sync();
-  return kth;
+  for (int i = lane; i < n; i += 64) {
+    const uint64_t k = w.idk[i];
+    if (k >= kth) L[atomicAdd(&w.kept, 1u)] = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - w.row[i]);
+  }
+  wave_sync();
+  return key_score(kth);
 }
 
-template <int QW>
-__device__ uint64_t wave_min_key(uint64_t* qbuf, int cnt, WaveSmem<QW>& w) {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-  auto load = [&](int i) { return __hip_atomic_load(qbuf + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
-  return wave_kth(load, cnt, cnt, w.hist);
+// cluster of stored row `row`: the number of j in [1, C) with offsets[j] <= row
+// (segments are contiguous and increasing; empty ones are skipped)
+__device__ inline int find_cluster(const int64_t* __restrict__ offsets, int C, int64_t row) {
+  const int lane = threadIdx.x & 63;
+  int c = 0;
+  for (int j0 = 1; j0 < C; j0 += 64) {
+    const int j = j0 + lane;
+    const bool le = j < C && offsets[j] <= row;
+    c += __popcll(__ballot(le));
+  }
+  return c;
 }
 
-template <int FMT, int KS, int NB, bool SHARED, int MODE>
-__global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
+// a wavefront-uniform value computed in vector registers, made scalar
+__device__ inline int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline float uniformf(float v) {
+  return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+
+// compile-time unrolled loop: f(std::integral_constant<int, i>) for i in [I, N)
+template <int I, int N>
+struct Unroll {
+  template <typename F>
+  __device__ __forceinline__ static void run(F&& f) {
+    if constexpr (I < N) {
+      f(std::integral_constant<int, I>{});
+      Unroll<I + 1, N>::run(f);
+    }
+  }
+};
+
+__device__ inline float max16(const f32x16& v) {
+  float a = fmaxf(fmaxf(v[0], v[1]), v[2]);
+  float b = fmaxf(fmaxf(v[3], v[4]), v[5]);
+  float c = fmaxf(fmaxf(v[6], v[7]), v[8]);
+  float d = fmaxf(fmaxf(v[9], v[10]), v[11]);
+  float e = fmaxf(fmaxf(v[12], v[13]), v[14]);
+  return fmaxf(fmaxf(fmaxf(a, b), fmaxf(c, d)), fmaxf(e, v[15]));
+}
+
+// tile row of accumulator element i for a lane of half h (v_mfma_f32_32x32x*
+// output layout: rows (i % 4) + 8 * (i / 4) + 4 * h, column = lane % 32)
+__device__ constexpr int acc_row(int i, int h) { return (i & 3) + 8 * (i >> 2) + 4 * h; }
+
+template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   using Op = MfmaOp<FMT>;
   using S = typename Op::S;
   using T = typename Op::T;
-  constexpr int QW = 32 * NB;  // queries per wavefront
+  constexpr int QW = 32 * NB;        // queries per wavefront
+  constexpr int U = DEFER ? 2 * P : P;  // unrolled steps per loop iteration (ring x accumulator parity)
 
   __shared__ WaveSmem<QW> s_wave[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int C = a.C;
+  const int half = lane >> 5, col = lane & 31;
   WaveSmem<QW>& w = s_wave[wave];
 
   // ---- workgroup -> four (query block, range) work items
@@ -195,7 +241,6 @@ __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
 
   for (int i = lane; i < QW; i += 64) {
     const int64_t q = q0 + i;
-    w.cnt[i] = 0;
     w.tau[i] = (q < a.m) ? (a.seed ? a.seed[q] : -INFINITY) : INFINITY;
   }
   wave_sync();
@@ -203,187 +248,218 @@ __global__ __launch_bounds__(256, 1) void k_score_select(ScoreArgs a) {
   const int64_t ntiles = a.n_pad / kRows;
   const int64_t nvirt = (ntiles + a.stride - 1) / a.stride;
   const int64_t v_begin = nvirt * r / a.R, v_end = nvirt * (r + 1) / a.R;
-  const int limit = a.cap - kRows;
-  const int half = lane >> 5, col = lane & 31;
+  const int64_t ns = nvirt * kRows;  // dense: row count of the sample
+  // a list takes at most 32 keys per tile; between two overflow checks at most U + 1 tiles
+  const int lim = a.cap - kRows * (U + 1);
 
-  if (v_begin < v_end) {
-    const int64_t tile_bytes = (int64_t)kRows * a.dp * Op::EB;
-    const int64_t kblock = 64 * Op::EPL * Op::EB;
-    const uint8_t* xl = a.xlow + (int64_t)lane * Op::EPL * Op::EB;
-    auto load_tile = [&](S (&dst)[KS], int64_t v) {
-      const uint8_t* p = xl + (v < v_end ? v : v_end - 1) * a.stride * tile_bytes;
+  int cnt[NB];
+  int64_t lbase[NB];  // first key slot of this lane's (query, range) list
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    cnt[nb] = 0;
+    const int64_t q = q0 + nb * 32 + col;
+    lbase[nb] = ((q < a.m ? q : 0) * a.R + r) * (int64_t)a.cap;
+  }
+
+  const int64_t tile_bytes = (int64_t)kRows * a.dp * Op::EB;
+  const int64_t kblock = 64 * Op::EPL * Op::EB;
+  const uint8_t* xl = a.xlow + (int64_t)lane * Op::EPL * Op::EB;
+
+  T bq[NB][KS];
+  float st[NB];      // s_c * t_{q,c} for this lane's queries (times the operand widening)
+  float inv_st[NB];  // 1 / st (exact: a power of two)
+  float tau_s[NB];   // thresholds in the accumulator domain
+
+  // --------------------------------------------------------------- epilogue
+  auto epilogue = [&](f32x16 (&A)[NB], int64_t vt, int64_t real_end) __attribute__((always_inline)) {
+    const int64_t base = vt * a.stride * kRows;  // first stored row of the tile
+    if (base + kRows > real_end) {              // last tile of a segment: mask its padding rows
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+        constexpr int nb = decltype(nbc)::value;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (base + acc_row(i, half) >= real_end) A[nb][i] = __builtin_nanf("");
+      });
+    }
+    if constexpr (MODE == kDense) {
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+        constexpr int nb = decltype(nbc)::value;
+        const int64_t q = q0 + nb * 32 + col;
+        if (q < a.m) {
+          float* drow = a.dense + q * ns + vt * kRows;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const float v = A[nb][i];
+            drow[acc_row(i, half)] = (v == v) ? v * st[nb] : -INFINITY;
+          }
+        }
+      });
+    } else {
+      float mx[NB];
+      bool any = false;
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+        constexpr int nb = decltype(nbc)::value;
+        mx[nb] = max16(A[nb]);
+        any |= mx[nb] >= tau_s[nb];
+      });
+      if (__ballot(any)) {
+        Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+          constexpr int nb = decltype(nbc)::value;
+          if (__ballot(mx[nb] >= tau_s[nb]) == 0) return;
+          int p = 0;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) p += A[nb][i] >= tau_s[nb] ? 1 : 0;
+          const int pp = __shfl_xor(p, 32);  // the other half of this query's lanes
+          int o = cnt[nb] + (half ? pp : 0);
+          uint64_t* L = a.buf + lbase[nb];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            if (A[nb][i] >= tau_s[nb]) {
+              L[o] = make_key(A[nb][i] * st[nb], (uint32_t)(base + acc_row(i, half)));
+              ++o;
+            }
+          }
+          cnt[nb] += p + pp;
+        });
+      }
+    }
+  };
+
+  // --------------------------------------------------------------- overflow
+  auto check_overflow = [&]() __attribute__((always_inline)) {
+    if constexpr (MODE == kFilter) {
+      bool full = false;
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) { full |= cnt[decltype(nbc)::value] > lim; });
+      if (__ballot(full) == 0) return;
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+        constexpr int nb = decltype(nbc)::value;
+        uint64_t fm = __ballot(cnt[nb] > lim) & 0xFFFFFFFFull;
+        while (fm) {
+          const int cc = __ffsll((unsigned long long)fm) - 1;
+          fm &= fm - 1;
+          const int n = __shfl(cnt[nb], cc);
+          const int64_t lb = __shfl(lbase[nb], cc);
+          const float tk = compact_list(a.buf + lb, n, a.kappa, a.ids, w);
+          const int lq = nb * 32 + cc;
+          if (lane == 0) w.tau[lq] = fmaxf(w.tau[lq], tk);
+          wave_sync();
+          if (col == cc) {
+            cnt[nb] = a.kappa;
+            tau_s[nb] = w.tau[lq] * inv_st[nb];
+          }
+        }
+      });
+    }
+  };
+
+  // --------------------------------------------------------------- segments
+  int64_t v = v_begin;
+  while (v < v_end) {
+    const int64_t row0 = v * a.stride * kRows;
+    const int c = find_cluster(a.offsets, a.C, row0);
+    const int64_t tiles_end = uniform64(a.offsets[c + 1]) / kRows;  // first tile after the segment
+    const int64_t v1 = std::min<int64_t>(v_end, (tiles_end + a.stride - 1) / a.stride);
+    const int64_t real_end = uniform64(a.seg_end[c]);
+    {
+      const float sc = uniformf(a.scale[c]) * (1.0f / (Op::kScale * Op::kScale));
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+        constexpr int nb = decltype(nbc)::value;
+        const int64_t q = q0 + nb * 32 + col;
+        const bool qv = q < a.m;
+        const uint8_t* qp = a.qhat + ((qv ? q : 0) * a.C + c) * (int64_t)a.dp * Op::EB +
+                            (int64_t)(half * Op::EPL) * Op::EB;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const S raw = *(const S*)(qp + (int64_t)(s * Op::KM) * Op::EB);
+          bq[nb][s] = qv ? Op::cvt(raw) : zero_op<T>();
+        }
+        st[nb] = sc * (qv ? a.qscale[q * a.C + c] : 1.0f);
+        inv_st[nb] = 1.0f / st[nb];
+        tau_s[nb] = w.tau[nb * 32 + col] * inv_st[nb];
+      });
+    }
+
+    const int64_t v0 = v;
+    auto load_tile = [&](S (&dst)[KS], int64_t vv) __attribute__((always_inline)) {
+      const uint8_t* p = xl + (vv < v1 ? vv : v1 - 1) * a.stride * tile_bytes;
 #pragma unroll
       for (int s = 0; s < KS; ++s) dst[s] = *(const S*)(p + s * kblock);
     };
-
-    T bq[NB][KS];
-    float st[NB];      // s_c * t_{q,c} for this lane's queries (times the operand widening)
-    float inv_st[NB];  // 1 / st (exact: a power of two)
-    float tau_s[NB];   // thresholds in the accumulator domain
-    auto refresh_tau = [&]() {
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) tau_s[nb] = w.tau[nb * 32 + col] * inv_st[nb];
-    };
-
-    // cluster walk: the tiles of a range are visited in increasing order
-    int c;
-    int64_t c_end;  // first stored row after cluster c
-    {
-      const int64_t row = v_begin * a.stride * kRows;
-      int lo = 0, hi = C - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (a.offsets[mid] <= row) lo = mid; else hi = mid - 1;
-      }
-      c = lo;
-      c_end = a.offsets[c + 1];
-    }
-    int cur_c = -1;
-    const int64_t ns = nvirt * kRows;  // dense row count of the sample
-
-    auto step = [&](S (&cur)[KS], S (&pf)[KS], int64_t vv) {
-      load_tile(pf, vv + 2);
-      const bool live = vv < v_end;
-      const int64_t t = (live ? vv : v_end - 1) * a.stride;  // tile index
-      const int64_t base = t * kRows;                          // its first stored row
-      if (live) {
-        while (base >= c_end) {
-          ++c;
-          c_end = a.offsets[c + 1];
-        }
-        if (c != cur_c) {
-          cur_c = c;
-          const float sc = a.scale[c] * (1.0f / (Op::kScale * Op::kScale));
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            const int64_t q = q0 + nb * 32 + col;
-            const bool qv = q < a.m;
-            const uint8_t* qp = a.qhat + ((qv ? q : 0) * C + c) * (int64_t)a.dp * Op::EB +
-                                (int64_t)(half * Op::EPL) * Op::EB;
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-              const S raw = *(const S*)(qp + (int64_t)(s * Op::KM) * Op::EB);
-              bq[nb][s] = qv ? Op::cvt(raw) : zero_op<T>();
-            }
-            st[nb] = sc * (qv ? a.qscale[q * C + c] : 1.0f);
-            inv_st[nb] = 1.0f / st[nb];
-          }
-          refresh_tau();
-        }
-      }
-      f32x16 acc[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x16{0};
+    auto mma_tile = [&](const S (&src)[KS], f32x16 (&A)[NB]) __attribute__((always_inline)) {
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) { A[decltype(nbc)::value] = f32x16{0}; });
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const T av = Op::cvt(cur[s]);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[nb] = Op::mma(av, bq[nb][s], acc[nb]);
-      }
-      if (!live) return;
-      // epilogue: lane holds query col of each block nb, tile rows (i%4) + 8*(i/4) + 4*half
-      if constexpr (MODE == kDense) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int64_t q = q0 + nb * 32 + col;
-          if (q >= a.m) continue;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int rt = (i & 3) + 8 * (i >> 2) + 4 * half;
-            const bool real = a.ids[base + rt] >= 0;
-            a.dense[q * ns + vv * kRows + rt] = real ? acc[nb][i] * st[nb] : -INFINITY;
-          }
-        }
-        return;
-      }
-      bool any = false;
-      float mx[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        mx[nb] = acc[nb][0];
-#pragma unroll
-        for (int i = 1; i < 16; ++i) mx[nb] = fmaxf(mx[nb], acc[nb][i]);
-        any |= mx[nb] >= tau_s[nb];
-      }
-      if (__ballot(any)) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          if (mx[nb] >= tau_s[nb]) {
-            const int lq = nb * 32 + col;
-            const int64_t q = q0 + lq;
-            uint64_t* qbuf = a.buf + ((q * a.R) + r) * (int64_t)kCap;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-              if (acc[nb][i] >= tau_s[nb]) {
-                const int32_t id = a.ids[base + (i & 3) + 8 * (i >> 2) + 4 * half];
-                if (id >= 0) {
-                  const float score = acc[nb][i] * st[nb];
-                  const int slot = atomicAdd(&w.cnt[lq], 1);
-                  qbuf[slot] = make_key(score, (uint32_t)id);
-                }
-              }
-            }
-          }
-        }
-        wave_sync();
-        // compaction of this wavefront's nearly full buffers
-        bool full = false;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) full |= w.cnt[nb * 32 + col] > limit;
-        if (__ballot(full)) {
-          for (int lq = 0; lq < QW; ++lq) {
-            const int cnt = w.cnt[lq];
-            if (cnt <= limit) continue;
-            uint64_t* qbuf = a.buf + (((q0 + lq) * a.R) + r) * (int64_t)kCap;
-            const float tk = key_score(wave_compact(qbuf, cnt, a.kappa, w));
-            if (lane == 0) {
-              w.cnt[lq] = a.kappa;
-              w.tau[lq] = fmaxf(w.tau[lq], tk);
-            }
-            wave_sync();
-          }
-          refresh_tau();
-        }
+        const T av = Op::cvt(src[s]);
+        Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+          constexpr int nb = decltype(nbc)::value;
+          A[nb] = Op::mma(av, bq[nb][s], A[nb]);
+        });
       }
     };
 
-    S b0[KS], b1[KS], b2[KS];
-    load_tile(b0, v_begin);
-    load_tile(b1, v_begin + 1);
-    for (int64_t v = v_begin; v < v_end; v += 3) {
-      step(b0, b2, v);
-      step(b1, b0, v + 1);
-      step(b2, b1, v + 2);
-    }
-  }
-  if constexpr (MODE == kDense) return;
+    S ring[P][KS];
+    Unroll<0, P - 1>::run([&](auto pc) __attribute__((always_inline)) { load_tile(ring[decltype(pc)::value], v0 + decltype(pc)::value); });
+    f32x16 acc0[NB], acc1[NB];
 
-  // ---- final
-  wave_sync();
-  for (int lq = 0; lq < QW; ++lq) {
-    const int64_t q = q0 + lq;
-    if (q >= a.m) break;
-    uint64_t* qbuf = a.buf + ((q * a.R) + r) * (int64_t)kCap;
-    const int cnt = w.cnt[lq];
-    if constexpr (MODE == kMain) {
-      // keep at most kappa keys per (query, range)
-      if (cnt > a.kappa) (void)wave_compact(qbuf, cnt, a.kappa, w);
-      if (lane == 0) a.cnt_out[q * a.R + r] = cnt < a.kappa ? cnt : a.kappa;
-    } else {
-      // publish how many this range kept (at most kappa_r) and the worst of them
-      if (cnt > 0) {
-        const int keep = cnt < a.kappa ? cnt : a.kappa;
-        const uint64_t worst = cnt > a.kappa ? wave_compact(qbuf, cnt, keep, w) : wave_min_key(qbuf, cnt, w);
-        if (lane == 0) {
-          atomicMin(&a.tau_ord[q], order_f32(key_score(worst)));
-          atomicAdd(&a.kcount[q], keep);
+    for (int64_t vb = v0; vb < v1; vb += U) {
+      // Loads and matrix-core steps run unconditionally (tiles past the
+      // segment re-read its last tile and are not filtered), so the memory
+      // counter waits are the same on every path through the loop.
+      Unroll<0, U>::run([&](auto uc) __attribute__((always_inline)) {
+        constexpr int u = decltype(uc)::value;
+        const int64_t vt = vb + u;
+        load_tile(ring[(u + P - 1) % P], vt + P - 1);
+        if constexpr (DEFER) {
+          // matrix core on tile vt, filter of tile vt - 1
+          if constexpr (u & 1) mma_tile(ring[u % P], acc1); else mma_tile(ring[u % P], acc0);
+          if ((u > 0 || vt > v0) && vt - 1 < v1) {
+            if constexpr (u & 1) epilogue(acc0, vt - 1, real_end); else epilogue(acc1, vt - 1, real_end);
+          }
+        } else {
+          mma_tile(ring[u % P], acc0);
+          if (vt < v1) epilogue(acc0, vt, real_end);
         }
+      });
+      check_overflow();
+    }
+    if constexpr (DEFER) {  // the last tile's filter, when the final step scored a real tile
+      if ((v1 - v0) % U == 0) {
+        epilogue(acc1, v1 - 1, real_end);  // U is even: the final step used acc1
+        check_overflow();
       }
+    }
+    v = v1;
+  }
+
+  if constexpr (MODE == kFilter) {
+    if (half == 0) {
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+        constexpr int nb = decltype(nbc)::value;
+        const int64_t q = q0 + nb * 32 + col;
+        if (q < a.m) a.cnt_out[q * a.R + r] = cnt[nb];
+      });
     }
   }
 }
 
-// choose the launch shape of S2/S3 for a scan over `rows` rows
+// Register budget per configuration (512 per lane at one wavefront per SIMD):
+// ring of P tiles, the query views, one or two accumulator sets.  Few queries
+// (memory-bound): deep ring, deferred filter.  Many queries (matrix-core bound,
+// NB = 4): the views take most registers, so the ring is shallow.  P is also
+// bounded by the 63 loads the vector memory counter tracks.
+template <int FMT, int KS, int NB>
+struct ScanCfg {
+  static constexpr int per_tile = KS * (int)sizeof(typename MfmaOp<FMT>::S) / 4;
+  static constexpr int views = NB * KS * (int)sizeof(typename MfmaOp<FMT>::T) / 4;
+  static constexpr bool defer = NB < 4;
+  static constexpr int budget = 400 - views - (defer ? 2 : 1) * NB * 16 - 48;
+  static constexpr int p0 = budget / per_tile;
+  static constexpr int pv = 63 / KS + 1;
+  static constexpr int p1 = p0 < pv ? p0 : pv;
+  static constexpr int P = p1 < 2 ? 2 : (p1 > 6 ? 6 : p1);
+};
+
+// launch shape of S2/S3 for one scan
 struct Shape {
   bool shared;  // the four wavefronts of a workgroup share one query block
   int nb;       // 32-query blocks per wavefront
@@ -393,25 +469,25 @@ struct Shape {
   int xcd_map;
 };
 
+template <int FMT, int KS, int NB, bool SHARED, int MODE>
+void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
+  using Cfg = ScanCfg<FMT, KS, NB>;
+  hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, Cfg::defer, 1>), dim3(sh.grid), dim3(256), 0, st, args);
+}
+
 template <int FMT, int KS, int MODE>
 void launch_score(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   if constexpr (FMT == GV_FP32) {
-    if (sh.shared)
-      hipLaunchKernelGGL((k_score_select<FMT, KS, 1, true, MODE>), dim3(sh.grid), dim3(256), 0, st, args);
-    else
-      hipLaunchKernelGGL((k_score_select<FMT, KS, 1, false, MODE>), dim3(sh.grid), dim3(256), 0, st, args);
+    if (sh.shared) launch_one<FMT, KS, 1, true, MODE>(sh, args, st);
+    else launch_one<FMT, KS, 1, false, MODE>(sh, args, st);
   } else {
-    if (sh.shared && sh.nb == 1)
-      hipLaunchKernelGGL((k_score_select<FMT, KS, 1, true, MODE>), dim3(sh.grid), dim3(256), 0, st, args);
-    else if (sh.shared)
-      hipLaunchKernelGGL((k_score_select<FMT, KS, 2, true, MODE>), dim3(sh.grid), dim3(256), 0, st, args);
+    if (sh.shared && sh.nb == 1) launch_one<FMT, KS, 1, true, MODE>(sh, args, st);
+    else if (sh.shared) launch_one<FMT, KS, 2, true, MODE>(sh, args, st);
     else if constexpr (KS <= 10) {
-      if (sh.nb == 4)
-        hipLaunchKernelGGL((k_score_select<FMT, KS, 4, false, MODE>), dim3(sh.grid), dim3(256), 0, st, args);
-      else
-        hipLaunchKernelGGL((k_score_select<FMT, KS, 2, false, MODE>), dim3(sh.grid), dim3(256), 0, st, args);
+      if (sh.nb == 4) launch_one<FMT, KS, 4, false, MODE>(sh, args, st);
+      else launch_one<FMT, KS, 2, false, MODE>(sh, args, st);
     } else {
-      hipLaunchKernelGGL((k_score_select<FMT, KS, 2, false, MODE>), dim3(sh.grid), dim3(256), 0, st, args);
+      launch_one<FMT, KS, 2, false, MODE>(sh, args, st);
     }
   }
 }
@@ -436,7 +512,7 @@ gv_status dispatch_ks(int dp, const Shape& sh, const ScoreArgs& args, hipStream_
 
 }  // namespace scan
 
-// per-format entry points (search_fp32.hip, search_fp16.hip, ...)
+// per-format entry points (scan_fp32.hip, scan_fp16.hip, ...)
 template <int FMT, int MODE>
 gv_status dispatch_scan(int dp, const scan::Shape& sh, const scan::ScoreArgs& args, hipStream_t st);
 

@@ -349,7 +349,7 @@ def test_compaction_path(gv, fmt, m):
     Qd = dev(Q)
     _, t, qhat = gv.project(model, fmt, Qd, want_qc=False)
     c1, d1 = gv.score_topk(idx, qhat, t, kappa)
-    gv.search_tuning(splits=4, qpw=0, cap=512)
+    gv.search_tuning(splits=4, qpw=0, cap=640)
     try:
         c2, d2 = gv.score_topk(idx, qhat, t, kappa)
     finally:
