@@ -269,8 +269,11 @@ Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C) {
   if (dp > 160 && sh.nb > 2) sh.nb = 2;  // keeps the query views of the longest rows in registers
   sh.nqb = (m + 32 * sh.nb - 1) / (32 * sh.nb);
   const int64_t ntiles = rows / kRows + C;
-  // about 1024 wavefronts (four per compute unit), at least 4 tiles per range
-  int64_t R = tuned_splits() > 0 ? tuned_splits() : std::max<int64_t>(1, 1024 / sh.nqb);
+  // about 1024 wavefronts (one per SIMD) when the query blocks share a workgroup's
+  // rows, 2048 (two rounds of workgroups, which evens out ranges that hold many
+  // survivors) otherwise; at least 4 tiles per range
+  const int64_t waves = sh.shared ? 1024 : 2048;
+  int64_t R = tuned_splits() > 0 ? tuned_splits() : std::max<int64_t>(1, waves / sh.nqb);
   R = std::min<int64_t>(R, std::max<int64_t>(1, ntiles / 4));
   R = std::min<int64_t>(R, kMaxLists);
   if (sh.shared) {
@@ -344,14 +347,8 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
   int Rmax = 1;
   for (size_t li = 0; li < levels.size(); ++li) {
     const int64_t s = levels[li];
-    Shape sh = choose_shape(fmt, idx->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
-    if (has_dense && li == 0) {
-      sh.R = sh.shared ? 4 : 1;  // dense scan of a small sample
-      sh.xcd_map = 0;
-      sh.grid = (int)(sh.shared ? sh.nqb : (sh.nqb + 3) / 4);
-    } else {
-      Rmax = std::max(Rmax, sh.R);
-    }
+    const Shape sh = choose_shape(fmt, idx->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
+    if (!(has_dense && li == 0)) Rmax = std::max(Rmax, sh.R);  // the dense scan writes no lists
     shapes.push_back(sh);
   }
   const int64_t ns = has_dense ? ((ntiles + levels[0] - 1) / levels[0]) * kRows : 0;

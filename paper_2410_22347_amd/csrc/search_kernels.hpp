@@ -114,21 +114,22 @@ __device__ uint64_t wave_kth(Load load, int cnt, int kappa, uint32_t* hist) {
   return prefix;
 }
 
-// LDS of one wavefront
-template <int QW>
+// LDS of one wavefront; CAPL = largest list a compaction stages
+template <int QW, int CAPL>
 struct WaveSmem {
   float tau[QW];
   uint32_t hist[256];
   uint32_t kept;
-  uint64_t idk[kCap];  // compaction: keys ordered by (score desc, id asc)
-  uint32_t row[kCap];  //             and the stored row of each
+  uint64_t idk[CAPL];  // compaction: keys ordered by (score desc, id asc)
+  uint32_t row[CAPL];  //             and the stored row of each
+  f32x16 acc[64];      // survivor extraction: one lane's 16 scores, indexed per lane
 };
 
 // Reduce the list L of n keys (n > keep) to its `keep` best by (score desc,
 // original id asc); the kept keys are rewritten to L[0..keep).  Returns the
 // score of the keep-th best.
-template <int QW>
-__device__ float compact_list(uint64_t* L, int n, int keep, const int32_t* __restrict__ ids, WaveSmem<QW>& w) {
+template <typename W>
+__device__ float compact_list(uint64_t* L, int n, int keep, const int32_t* __restrict__ ids, W& w) {
   const int lane = threadIdx.x & 63;
   // the keys were stored by lanes of this wavefront: make them visible and
   // read them coherently from L2
@@ -187,6 +188,12 @@ struct Unroll {
   }
 };
 
+// value of x in the lane 32 apart (lanes l and l ^ 32 exchange)
+__device__ inline int other_half(int x) {
+  const auto r = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+  return (int)((threadIdx.x & 32) ? r[0] : r[1]);
+}
+
 __device__ inline float max16(const f32x16& v) {
   float a = fmaxf(fmaxf(v[0], v[1]), v[2]);
   float b = fmaxf(fmaxf(v[3], v[4]), v[5]);
@@ -208,10 +215,11 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   constexpr int QW = 32 * NB;        // queries per wavefront
   constexpr int U = DEFER ? 2 * P : P;  // unrolled steps per loop iteration (ring x accumulator parity)
 
-  __shared__ WaveSmem<QW> s_wave[4];
+  constexpr int CAPL = OCC >= 2 ? kCap / 2 : kCap;  // two workgroups per CU need the smaller staging
+  __shared__ WaveSmem<QW, CAPL> s_wave[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
-  WaveSmem<QW>& w = s_wave[wave];
+  WaveSmem<QW, CAPL>& w = s_wave[wave];
 
   // ---- workgroup -> four (query block, range) work items
   int qb, r;
@@ -306,16 +314,22 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
         Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
           constexpr int nb = decltype(nbc)::value;
           if (__ballot(mx[nb] >= tau_s[nb]) == 0) return;
-          int p = 0;
+          const float t = tau_s[nb];
+          uint32_t mask = 0;  // survivors among this lane's 16 scores
 #pragma unroll
-          for (int i = 0; i < 16; ++i) p += A[nb][i] >= tau_s[nb] ? 1 : 0;
-          const int pp = __shfl_xor(p, 32);  // the other half of this query's lanes
+          for (int i = 0; i < 16; ++i) mask |= A[nb][i] >= t ? (1u << i) : 0u;
+          const int p = __builtin_popcount(mask);
+          const int pp = other_half(p);  // the other lane holding this query
           int o = cnt[nb] + (half ? pp : 0);
           uint64_t* L = a.buf + lbase[nb];
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            if (A[nb][i] >= tau_s[nb]) {
-              L[o] = make_key(A[nb][i] * st[nb], (uint32_t)(base + acc_row(i, half)));
+          w.acc[lane] = A[nb];  // scores by per-lane index go through LDS
+          const float* my = reinterpret_cast<const float*>(&w.acc[lane]);
+          while (__ballot(mask != 0)) {  // as many rounds as the busiest lane has survivors
+            if (mask) {
+              const int i = __builtin_ctz(mask);
+              mask &= mask - 1;
+              const float v = my[i];
+              L[o] = make_key(v * st[nb], (uint32_t)(base + (i & 3) + 8 * (i >> 2) + 4 * half));
               ++o;
             }
           }
@@ -444,19 +458,20 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
 
 // Register budget per configuration (512 per lane at one wavefront per SIMD):
 // ring of P tiles, the query views, one or two accumulator sets.  Few queries
-// (memory-bound): deep ring, deferred filter.  Many queries (matrix-core bound,
-// NB = 4): the views take most registers, so the ring is shallow.  P is also
-// bounded by the 63 loads the vector memory counter tracks.
+// (memory-bound): a ring of up to four tiles (deeper rings measured no faster)
+// and the deferred filter.  Many queries (matrix-core bound, NB = 4): the views
+// take most registers, so the ring is shallow and the filter is not deferred.
+// P is also bounded by the 63 loads the vector memory counter tracks.
 template <int FMT, int KS, int NB>
 struct ScanCfg {
   static constexpr int per_tile = KS * (int)sizeof(typename MfmaOp<FMT>::S) / 4;
   static constexpr int views = NB * KS * (int)sizeof(typename MfmaOp<FMT>::T) / 4;
   static constexpr bool defer = NB < 4;
-  static constexpr int budget = 400 - views - (defer ? 2 : 1) * NB * 16 - 48;
+  static constexpr int budget = 440 - views - (defer ? 2 : 1) * NB * 16 - 48;
   static constexpr int p0 = budget / per_tile;
   static constexpr int pv = 63 / KS + 1;
   static constexpr int p1 = p0 < pv ? p0 : pv;
-  static constexpr int P = p1 < 2 ? 2 : (p1 > 6 ? 6 : p1);
+  static constexpr int P = p1 < 2 ? 2 : (p1 > 4 ? 4 : p1);
 };
 
 // launch shape of S2/S3 for one scan
