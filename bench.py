@@ -1,18 +1,29 @@
 """Benchmark of the GleanVec search path on one MI355X.
 
 Workload (default): n = 10M database vectors, D = 768 -> d = 160, C = 32
-clusters, kappa = 200, k = 10 -- the shape of the paper's largest OOD set
-(RQA-10M-OOD, Table 1) -- drawn from a seeded 32-component Gaussian mixture
-with decaying spectra and OOD queries (shifted means, rotated covariance).
+clusters, kappa = 200, k = 10, FP16 reduced storage, query batches of 4096 --
+the shape of the paper's largest out-of-distribution set (RQA-10M-OOD,
+Table 1) -- drawn from a seeded 32-component Gaussian mixture with decaying
+spectra and OOD queries (shifted means, rotated covariance).
 
 A step is one query batch through the whole search path (S1 projection, S2/S3
-scoring with top-kappa, merge, S4 rerank) against the index resident in HBM.
-The index build (fit, encode) runs once before timing and is reported
-separately.  Prints one JSON line (rank 0, N = 1).
+grouped scoring with the per-query top-kappa filter, select, S4 rerank) against
+the index resident in HBM, with the queries already in device memory.  The
+index build (fit, encode) runs once before timing and is reported separately.
+Prints one JSON line.
+
+roofline: the dominant kernel is the full-database scan (S2 + S3).  Its average
+launch duration is measured inside the timed region with HIP events recorded
+by the library on the stream the kernel runs on.  Algorithmic work per launch:
+2 m n d FLOP (matrix-core bound at large m) or n d b bytes (HBM bound at small
+m).  traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
+counter runs, scaled by the same counters on a plain 1 GiB copy, read from
+profiles/ when they were taken on the current kernel source, else null.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,8 +35,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "QPS at 10-recall@10≥0.9, 10M×768→160, C=32; achieved HBM GB/s vs peak"
-PEAK = {"hbm_gbs": 8000.0, "fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}  # TFLOP/s
+PEAK_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp8": 2500.0}  # fp8 is widened to the fp16 matrix core
+PEAK_HBM_GBS = 8000.0
 BYTES = {"fp32": 4, "fp16": 2, "bf16": 2, "fp8": 1}
+DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp8": "fp8-e4m3 (f16 matrix core)"}
+# sources of the scanning kernel: a traffic record taken on other sources is stale
+KERNEL_SOURCES = ["paper_2410_22347_amd/csrc/search_kernels.hpp", "paper_2410_22347_amd/csrc/search_common.hpp",
+                  "paper_2410_22347_amd/csrc/common.hpp", "paper_2410_22347_amd/csrc/scan_fp16.hip",
+                  "paper_2410_22347_amd/csrc/search.hip"]
 
 
 def log(*a):
@@ -38,17 +55,18 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mix32-10m-d768")
-    ap.add_argument("--n", type=int, default=0, help="override database size (debug)")
+    ap.add_argument("--n", type=int, default=0, help="override the database size (smaller runs)")
     ap.add_argument("--fmt", default="fp16")
     ap.add_argument("--m", type=int, default=4096)
-    ap.add_argument("--sweep", action="store_true", help="also time every format at m = 1, 64, 4096")
-    ap.add_argument("--single-queries", type=int, default=200)
+    ap.add_argument("--kappa", type=int, default=0, help="override kappa")
+    ap.add_argument("--sweep", action="store_true", help="also time every format at m = 1, 64, 4096 (stderr + 'sweep')")
+    ap.add_argument("--single-queries", type=int, default=200, help="steps at m = 1 in the sweep")
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1_000_000)
     ap.add_argument("--cpu-queries", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run a 1 GiB device-to-device copy (known traffic) before timing, for counter calibration")
+                    help="run 3 plain 1 GiB device copies before timing (counter calibration runs)")
     return ap.parse_args()
 
 
@@ -72,8 +90,10 @@ def recall(found, truth, K=10):
     return float(np.mean([len(set(f[:K].tolist()) & set(g[:K].tolist())) / K for f, g in zip(found, truth)]))
 
 
-def time_search(gv, model, index, Qpool, m, k, kappa, steps, warmup, profile=True):
-    """Wall-clock time of `steps` batches of m queries (rotating through the pool)."""
+def time_search(gv, model, index, Qpool, m, k, kappa, steps, warmup):
+    """Wall-clock time of `steps` batches of m queries (rotating through the
+    pool), and the average duration of the full scan and of the final select
+    from the library's HIP events."""
     import torch
     nb = max(1, Qpool.shape[0] // m)
     batches = [Qpool[(i % nb) * m:(i % nb) * m + m] for i in range(nb)]
@@ -81,8 +101,7 @@ def time_search(gv, model, index, Qpool, m, k, kappa, steps, warmup, profile=Tru
         gv.search(model, index, batches[i % nb], k, kappa)
     torch.cuda.synchronize()
     gv.profile_read()
-    if profile:
-        gv.profile_enable(True)
+    gv.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -91,7 +110,28 @@ def time_search(gv, model, index, Qpool, m, k, kappa, steps, warmup, profile=Tru
     dt = time.perf_counter() - t0
     gv.profile_enable(False)
     ms_s, n_s, ms_m, n_m = gv.profile_read()
-    return dt, (ms_s / max(n_s, 1)), (ms_m / max(n_m, 1))
+    return dt, ms_s / max(n_s, 1), ms_m / max(n_m, 1)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_record(fmt, m, workload):
+    """HBM bytes per launch of the full scan from a committed counter summary,
+    if it was taken on this kernel source and workload."""
+    path = os.path.join(ROOT, "profiles", f"k_scan_full_{fmt}_m{m}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != source_hash():
+        return None, "kernel source changed since the counters were taken"
+    return rec.get("hbm_bytes_per_launch"), os.path.relpath(path, ROOT)
 
 
 def cpu_baseline(X, geom, wl, m_s, n_s):
@@ -111,15 +151,16 @@ def cpu_baseline(X, geom, wl, m_s, n_s):
     per_query_full = dt / m_s * (wl.n / n_s)
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     return {"value": 1.0 / per_query_full, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"FP64 oracle S1-S4 (fp16 storage) for {m_s} queries over the first {n_s} of {wl.n} rows, "
-                      f"{dt:.2f} s, scaled linearly to n = {wl.n}",
-            "nproc": os.cpu_count()}
+            "sample": f"FP64 oracle S1-S4 (fp16 storage) for {m_s} queries over the first {n_s} of {wl.n} rows "
+                      f"(model fitted on 20000 of them), {dt:.2f} s, scaled linearly in n to {wl.n} rows",
+            "host_cpus": os.cpu_count()}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (this path does not shard)",
+              file=sys.stderr)
         return 2
     import torch
     import synth
@@ -128,8 +169,9 @@ def main():
     wl = synth.WORKLOADS[a.workload]
     if a.n:
         wl = synth.Workload(**{**wl.__dict__, "n": a.n})
+    kappa = a.kappa or wl.kappa
     dev = torch.device("cuda:0")
-    log(f"[bench] workload {wl.name} n={wl.n} D={wl.D} d={wl.d} C={wl.C}")
+    log(f"[bench] workload {wl.name} n={wl.n} D={wl.D} d={wl.d} C={wl.C} kappa={kappa}")
     geom = synth.make_geometry(wl.cfg, wl.D, wl.J, wl.law)
     t0 = time.perf_counter()
     X = synth.draw_torch(geom, wl.n, synth.S_DB, dev)
@@ -143,12 +185,13 @@ def main():
 
     t0 = time.perf_counter()
     model = gv.fit(XL, QL, wl.d, wl.C, seed=synth.fit_seed(wl.cfg))
+    torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
     del XL
-    log(f"[bench] fit {t_fit:.1f} s")
+    log(f"[bench] fit {t_fit:.2f} s")
 
     if a.calibrate_copy:
-        src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)   # 1 GiB
+        src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
@@ -158,13 +201,11 @@ def main():
 
     nrq = min(a.recall_queries, QT.shape[0])
     gt = exact_topk_device(X, QT[:nrq], wl.k) if nrq > 0 else None
-    log("[bench] ground truth done")
 
     fmts = ["fp32", "fp16", "bf16", "fp8"] if a.sweep else [a.fmt]
     if a.fmt not in fmts:
         fmts.append(a.fmt)
-    sweep = []
-    main_rec = None
+    sweep, main_rec = [], None
     for fmt in fmts:
         t0 = time.perf_counter()
         index = gv.encode(model, X, fmt)
@@ -172,45 +213,50 @@ def main():
         t_enc = time.perf_counter() - t0
         rec = None
         if gt is not None:
-            ids, _ = gv.search(model, index, QT[:nrq], wl.k, wl.kappa)
+            ids, _ = gv.search(model, index, QT[:nrq], wl.k, kappa)
             rec = recall(ids.cpu().numpy(), gt)
         log(f"[bench] {fmt}: encode {t_enc:.2f} s, 10-recall@10 = {rec}")
         ms_list = [a.m] if not a.sweep else sorted({1, 64, 4096, a.m})
         for m in ms_list:
-            if m == 1:
+            if fmt == a.fmt and m == a.m:
+                steps, warm = a.steps, a.warmup
+            elif m == 1:
                 steps, warm = a.single_queries, 5
             else:
-                steps, warm = (a.steps, a.warmup) if (fmt == a.fmt and m == a.m) else (max(3, a.steps // 4), 2)
-            dt, ms_score, ms_merge = time_search(gv, model, index, QT, m, wl.k, wl.kappa, steps, warm)
-            qps = m * steps / dt
-            ent = {"fmt": fmt, "m": m, "qps": qps, "ms_per_batch": dt / steps * 1e3,
-                   "score_kernel_ms": ms_score, "merge_ms": ms_merge, "recall": rec, "encode_s": t_enc}
+                steps, warm = max(3, a.steps // 4), 2
+            dt, ms_scan, ms_sel = time_search(gv, model, index, QT, m, wl.k, kappa, steps, warm)
             b = BYTES[fmt]
-            hbm = wl.n * wl.d * b / (ms_score * 1e-3) / 1e9
-            flops = 2.0 * m * wl.n * wl.d / (ms_score * 1e-3) / 1e12
-            ent["score_hbm_gbs"] = hbm
-            ent["score_tflops"] = flops
+            ent = {"fmt": fmt, "m": m, "qps": m * steps / dt, "ms_per_batch": dt / steps * 1e3,
+                   "scan_ms": ms_scan, "select_ms": ms_sel, "recall_at_10": rec, "encode_s": t_enc,
+                   "scan_hbm_gbs": wl.n * wl.d * b / (ms_scan * 1e-3) / 1e9,
+                   "scan_tflops": 2.0 * m * wl.n * wl.d / (ms_scan * 1e-3) / 1e12}
             sweep.append(ent)
-            log(f"[bench]   {fmt} m={m}: {qps:,.0f} q/s, batch {dt / steps * 1e3:.3f} ms, "
-                f"score kernel {ms_score:.3f} ms ({hbm:,.0f} GB/s, {flops:,.1f} TFLOP/s), merge {ms_merge:.3f} ms")
+            log(f"[bench]   {fmt} m={m}: {ent['qps']:,.0f} q/s, batch {ent['ms_per_batch']:.3f} ms, full scan "
+                f"{ms_scan:.3f} ms ({ent['scan_hbm_gbs']:,.0f} GB/s, {ent['scan_tflops']:,.1f} TFLOP/s), "
+                f"select {ms_sel:.3f} ms")
             if fmt == a.fmt and m == a.m:
                 main_rec = (ent, dt, steps)
         del index
         torch.cuda.empty_cache()
 
     ent, dt, steps = main_rec
-    m = a.m
-    b = BYTES[a.fmt]
-    avg_s = ent["score_kernel_ms"] * 1e-3
-    if m <= 64:
-        roof = {"bound": "hbm", "achieved": wl.n * wl.d * b / avg_s / 1e9, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
+    m, b = a.m, BYTES[a.fmt]
+    avg_s = ent["scan_ms"] * 1e-3
+    flops = 2.0 * m * wl.n * wl.d
+    nbytes = float(wl.n * wl.d * b)
+    # binding resource: matrix core when the flop time at peak exceeds the byte time at peak
+    if flops / (PEAK_TFLOPS[a.fmt] * 1e12) > nbytes / (PEAK_HBM_GBS * 1e9):
+        roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": PEAK_TFLOPS[a.fmt], "unit": "TFLOP/s"}
     else:
-        roof = {"bound": "mfma", "achieved": 2.0 * m * wl.n * wl.d / avg_s / 1e12, "peak": PEAK[a.fmt],
-                "unit": "TFLOP/s"}
+        roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = "k_score_select"
-    roof["avg_launch_ms"] = ent["score_kernel_ms"]
+    traffic, traffic_src = traffic_record(a.fmt, m, wl.name)
+    roof["traffic"] = traffic
+    roof["traffic_source"] = traffic_src
+    roof["kernel"] = "k_scan (full database, S2 + S3)"
+    roof["avg_launch_ms"] = ent["scan_ms"]
+    roof["algorithmic"] = {"flop_per_launch": flops, "bytes_per_launch": nbytes,
+                           "hbm_gbs": nbytes / avg_s / 1e9}
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -228,12 +274,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f16 (f32 accumulate)", "bf16": "bf16 (f32 accumulate)",
-                  "fp8": "fp8-e4m3 (f32 accumulate)"}[a.fmt],
+        "dtype": DTYPE[a.fmt],
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": wl.n, "D": wl.D, "d": wl.d, "C": wl.C, "kappa": wl.kappa,
-                   "k": wl.k, "batch": m, "storage": a.fmt},
-        "recall_at_10": ent["recall"],
+        "config": {"workload": wl.name, "n": wl.n, "D": wl.D, "d": wl.d, "C": wl.C, "kappa": kappa, "k": wl.k,
+                   "batch": m, "storage": a.fmt},
+        "recall_at_10": ent["recall_at_10"],
         "roofline": roof,
         "cpu_baseline": cpu,
         "build": {"datagen_s": t_gen, "fit_s": t_fit, "encode_s": ent["encode_s"]},

@@ -207,7 +207,7 @@ __device__ inline float max16(const f32x16& v) {
 // output layout: rows (i % 4) + 8 * (i / 4) + 4 * h, column = lane % 32)
 __device__ constexpr int acc_row(int i, int h) { return (i & 3) + 8 * (i >> 2) + 4 * h; }
 
-template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC>
+template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC, bool FULL>
 __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   using Op = MfmaOp<FMT>;
   using S = typename Op::S;
@@ -253,8 +253,9 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   }
   wave_sync();
 
+  const int64_t stride = FULL ? 1 : a.stride;  // FULL: the scan of the whole database
   const int64_t ntiles = a.n_pad / kRows;
-  const int64_t nvirt = (ntiles + a.stride - 1) / a.stride;
+  const int64_t nvirt = (ntiles + stride - 1) / stride;
   const int64_t v_begin = nvirt * r / a.R, v_end = nvirt * (r + 1) / a.R;
   const int64_t ns = nvirt * kRows;  // dense: row count of the sample
   // a list takes at most 32 keys per tile; between two overflow checks at most U + 1 tiles
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
 
   // --------------------------------------------------------------- epilogue
   auto epilogue = [&](f32x16 (&A)[NB], int64_t vt, int64_t real_end) __attribute__((always_inline)) {
-    const int64_t base = vt * a.stride * kRows;  // first stored row of the tile
+    const int64_t base = vt * stride * kRows;  // first stored row of the tile
     if (base + kRows > real_end) {              // last tile of a segment: mask its padding rows
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
         constexpr int nb = decltype(nbc)::value;
@@ -369,10 +370,10 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   // --------------------------------------------------------------- segments
   int64_t v = v_begin;
   while (v < v_end) {
-    const int64_t row0 = v * a.stride * kRows;
+    const int64_t row0 = v * stride * kRows;
     const int c = find_cluster(a.offsets, a.C, row0);
     const int64_t tiles_end = uniform64(a.offsets[c + 1]) / kRows;  // first tile after the segment
-    const int64_t v1 = std::min<int64_t>(v_end, (tiles_end + a.stride - 1) / a.stride);
+    const int64_t v1 = std::min<int64_t>(v_end, (tiles_end + stride - 1) / stride);
     const int64_t real_end = uniform64(a.seg_end[c]);
     {
       const float sc = uniformf(a.scale[c]) * (1.0f / (Op::kScale * Op::kScale));
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
 
     const int64_t v0 = v;
     auto load_tile = [&](S (&dst)[KS], int64_t vv) __attribute__((always_inline)) {
-      const uint8_t* p = xl + (vv < v1 ? vv : v1 - 1) * a.stride * tile_bytes;
+      const uint8_t* p = xl + (vv < v1 ? vv : v1 - 1) * stride * tile_bytes;
 #pragma unroll
       for (int s = 0; s < KS; ++s) dst[s] = *(const S*)(p + s * kblock);
     };
@@ -487,7 +488,12 @@ struct Shape {
 template <int FMT, int KS, int NB, bool SHARED, int MODE>
 void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   using Cfg = ScanCfg<FMT, KS, NB>;
-  hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, Cfg::defer, 1>), dim3(sh.grid), dim3(256), 0, st, args);
+  if (MODE == kFilter && args.stride == 1)
+    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, Cfg::defer, 1, true>), dim3(sh.grid), dim3(256), 0, st,
+                       args);
+  else
+    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, Cfg::defer, 1, false>), dim3(sh.grid), dim3(256), 0,
+                       st, args);
 }
 
 template <int FMT, int KS, int MODE>
