@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1_000_000)
     ap.add_argument("--cpu-queries", type=int, default=32)
+    ap.add_argument("--splits", type=int, default=0, help="override the row ranges per query block (0: automatic)")
+    ap.add_argument("--qpw", type=int, default=0, help="override the queries per wavefront (0: automatic)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run 3 plain 1 GiB device copies before timing (counter calibration runs)")
     return ap.parse_args()
@@ -199,6 +201,8 @@ def main():
         del src, dst
         log("[bench] calibration copy: 3 x 1 GiB")
 
+    if a.splits or a.qpw:
+        gv.search_tuning(splits=a.splits, qpw=a.qpw)
     nrq = min(a.recall_queries, QT.shape[0])
     gt = exact_topk_device(X, QT[:nrq], wl.k) if nrq > 0 else None
 

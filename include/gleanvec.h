@@ -257,15 +257,57 @@ int32_t gv_padded_dim(int32_t d);
 
 /*
  * gv_profile_enable / gv_profile_read -- measurement hooks for benchmarks.
- * While enabled (on != 0), every scoring launch of S2/S3 and every merge launch
- * is bracketed by HIP events recorded on the stream it runs on.
- * gv_profile_read waits for the recorded events, returns the summed durations
- * (milliseconds) and launch counts of the scoring kernel and of the merge
- * kernels (any pointer may be NULL), and clears the record.  Off by default;
- * enabling it costs two event records per launch.
+ * While enabled (on != 0), every scan of the whole database (S2/S3) and every
+ * final top-kappa select is bracketed by HIP events recorded on the stream it
+ * runs on.  gv_profile_read waits for the recorded events, returns the summed
+ * durations (milliseconds) and launch counts of the scan and of the select
+ * (any pointer may be NULL), and clears the record.  Off by default; enabling
+ * it costs two event records per launch.
  */
 gv_status gv_profile_enable(int32_t on);
 gv_status gv_profile_read(double* ms_score, int64_t* n_score, double* ms_merge, int64_t* n_merge);
+
+/* ------------------------------------------------------------------ loss */
+
+/*
+ * gv_tags -- cluster tags of rows (the cluster-tag equation of Section 4):
+ * tags[i] = arg-max_c <x_i, mu_c> in FP64, lowest c on ties.
+ * X device n x D FP32 (D of the model); tags device n uint8.
+ * Errors: GV_EINVAL, GV_ENOTFIT, GV_ENOMEM, GV_EDEVICE.
+ */
+gv_status gv_tags(const gv_model* model, const float* X, int64_t n, uint8_t* tags, void* stream);
+
+/*
+ * gv_moments -- uncentered second-moment sums (Section 3, the statistics of
+ * the loss rewrite): K[c] = sum over rows v of V with tags[i] == c of v v^T,
+ * FP64 accumulation of exact FP32 products.
+ * V device n x D FP32; tags device n uint8 (< C), or NULL with C == 1 (every
+ * row; n == 0 needs no tags); K device C x D x D FP64, overwritten.
+ * Synchronises `stream`.
+ * Errors: GV_EINVAL (tag >= C, bad sizes), GV_ENOMEM, GV_EDEVICE.
+ */
+gv_status gv_moments(const float* V, int64_t n, int32_t D, const uint8_t* tags, int32_t C, double* K,
+                     void* stream);
+
+/*
+ * gv_loss_grad -- the inner-product approximation loss of Problem 3 summed
+ * over clusters, and its gradient, through the second-moment rewrite of
+ * Section 3 (Eq. 5):
+ *   L = (1/N) sum_c sum_q sum_{x in X_c} (<A_c q, B_c x> - <q, x>)^2
+ *     = (1/N) sum_c <K_Q M_c K_c, M_c>_F,        M_c = A_c^T B_c - I,
+ *   dL/dA_c = (2/N) B_c K_c M_c^T K_Q,   dL/dB_c = (2/N) A_c K_Q M_c K_c,
+ * with K_Q = sum_q q q^T and K_c = sum_{x in X_c} x x^T (sums, e.g. from
+ * gv_moments).  Evaluated in FP64 with products of at most d x D x D.
+ * A, B    device C x d x D FP32 (row c*d + i is row i of A_c / B_c).
+ * KQ      device D x D FP64; KX device C x D x D FP64 (symmetric).
+ * n_pairs N > 0.
+ * loss    device FP64 scalar; dA, dB device C x d x D FP32, either may be
+ *         NULL (not computed).
+ * Errors: GV_EINVAL (sizes, NULL loss/A/B/KQ/KX, N not positive and finite),
+ * GV_ENOMEM, GV_EDEVICE.
+ */
+gv_status gv_loss_grad(int32_t C, int32_t d, int32_t D, const float* A, const float* B, const double* KQ,
+                       const double* KX, double n_pairs, double* loss, float* dA, float* dB, void* stream);
 
 /*
  * gv_host_eigh -- the host FP64 symmetric eigensolver the fit uses for the

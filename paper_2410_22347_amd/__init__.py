@@ -28,7 +28,7 @@ EXPORTED = [
     "gv_model_export", "gv_model_stats", "gv_model_destroy", "gv_encode", "gv_index_shape",
     "gv_index_export", "gv_index_destroy", "gv_search", "gv_project", "gv_score_topk",
     "gv_rerank", "gv_search_tuning", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
-    "gv_padded_dim",
+    "gv_padded_dim", "gv_tags", "gv_moments", "gv_loss_grad",
 ]
 
 
@@ -81,6 +81,9 @@ _sig("gv_search_tuning", [_i32, _i32, _i32])
 _sig("gv_padded_dim", [_i32], _i32)
 _sig("gv_host_eigh", [_i32, _vp, _vp, _vp])
 _sig("gv_profile_enable", [_i32])
+_sig("gv_tags", [_vp, _vp, _i64, _vp, _vp])
+_sig("gv_moments", [_vp, _i64, _i32, _vp, _i32, _vp, _vp])
+_sig("gv_loss_grad", [_i32, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp])
 _sig("gv_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(_i64)])
 
@@ -288,6 +291,82 @@ def profile_read():
     _check(_lib.gv_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
            "gv_profile_read")
     return a.value, b.value, c.value, d.value
+
+
+def tags(model: Model, X):
+    """Cluster tags arg-max_c <x, mu_c> (FP64, lowest c on ties) as a uint8 CUDA tensor."""
+    import torch
+    X = _dev_f32(X)
+    if X.shape[1] != model.D:
+        raise ValueError("X has the wrong dimension")
+    out = torch.empty((X.shape[0],), dtype=torch.uint8, device=X.device)
+    _check(_lib.gv_tags(model._h, _ptr(X), X.shape[0], _ptr(out), _stream()), "gv_tags")
+    return out
+
+
+def moments(V, tags_=None, C: int = 1):
+    """Uncentered second-moment sums K[c] = sum_{tag == c} v v^T (FP64, C x D x D)."""
+    import torch
+    V = _dev_f32(V)
+    if tags_ is not None and not (tags_.is_cuda and tags_.dtype == torch.uint8 and tags_.is_contiguous()
+                                  and tags_.shape == (V.shape[0],)):
+        raise ValueError("tags must be a contiguous uint8 CUDA tensor with one entry per row")
+    D = V.shape[1]
+    K = torch.empty((C, D, D), dtype=torch.float64, device=V.device)
+    _check(_lib.gv_moments(_ptr(V), V.shape[0], D, _ptr(tags_), C, _ptr(K), _stream()), "gv_moments")
+    return K
+
+
+def loss_grad(A, B, KQ, KX, n_pairs: float, grads: bool = True):
+    """(loss, dA, dB) of the inner-product approximation loss (Gram form); see gv_loss_grad.
+    A, B: float32 CUDA (C, d, D); KQ: float64 (D, D); KX: float64 (C, D, D)."""
+    import torch
+    for t, dt, nd in ((A, torch.float32, 3), (B, torch.float32, 3), (KQ, torch.float64, 2), (KX, torch.float64, 3)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and t.dim() == nd):
+            raise ValueError("loss_grad: expected contiguous CUDA tensors A, B (float32, C x d x D), "
+                             "KQ (float64, D x D), KX (float64, C x D x D)")
+    C, d, D = A.shape
+    if B.shape != A.shape or KQ.shape != (D, D) or KX.shape != (C, D, D):
+        raise ValueError("loss_grad: shapes differ")
+    loss = torch.empty((), dtype=torch.float64, device=A.device)
+    dA = torch.empty_like(A) if grads else None
+    dB = torch.empty_like(B) if grads else None
+    _check(_lib.gv_loss_grad(C, d, D, _ptr(A), _ptr(B), _ptr(KQ), _ptr(KX), float(n_pairs), _ptr(loss), _ptr(dA),
+                             _ptr(dB), _stream()), "gv_loss_grad")
+    return loss, dA, dB
+
+
+def _make_loss_fn():
+    import torch
+
+    class GleanLoss(torch.autograd.Function):
+        """torch.autograd.Function over gv_loss_grad: forward returns the loss
+        (float64 scalar); the gradient with respect to A and B comes from the
+        same library call, scaled by the incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, A, B, KQ, KX, n_pairs):
+            loss, dA, dB = loss_grad(A.detach().contiguous(), B.detach().contiguous(), KQ, KX, n_pairs)
+            ctx.save_for_backward(dA, dB)
+            return loss
+
+        @staticmethod
+        def backward(ctx, g):
+            dA, dB = ctx.saved_tensors
+            return (g * dA).to(dA.dtype), (g * dB).to(dB.dtype), None, None, None
+
+    return GleanLoss
+
+
+_loss_fn = None
+
+
+def gleanvec_loss(A, B, KQ, KX, n_pairs: float):
+    """Differentiable loss of the per-cluster projections A, B (see GleanLoss)."""
+    global _loss_fn
+    if _loss_fn is None:
+        _loss_fn = _make_loss_fn()
+    return _loss_fn.apply(A, B, KQ, KX, n_pairs)
 
 
 def status_string(code: int) -> str:

@@ -1,5 +1,6 @@
 // C ABI of the library: argument validation, handle lifetime and the
 // sequencing of the device stages.  No exception crosses this boundary.
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <mutex>
@@ -380,6 +381,35 @@ gv_status gv_project(const gv_model* model, gv_format fmt, const float* Q, int64
     if (m == 0) return GV_OK;
     GV_REQUIRE(Q && t && qhat, "gv_project: NULL argument");
     return project_impl(model, fmt, Q, m, qc, t, qhat, (hipStream_t)stream);
+  });
+}
+
+gv_status gv_tags(const gv_model* model, const float* X, int64_t n, uint8_t* tags, void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(model)) return GV_ENOTFIT;
+    GV_REQUIRE(n >= 0, "gv_tags: n < 0");
+    if (n == 0) return GV_OK;
+    GV_REQUIRE(X && tags, "gv_tags: NULL argument");
+    return tags_impl(model, X, n, tags, (hipStream_t)stream);
+  });
+}
+
+gv_status gv_moments(const float* V, int64_t n, int32_t D, const uint8_t* tags, int32_t C, double* K, void* stream) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(n >= 0 && D >= 1 && C >= 1 && C <= 256, "gv_moments: bad sizes");
+    GV_REQUIRE(tags || C == 1 || n == 0, "gv_moments: C must be 1 without tags");
+    GV_REQUIRE(K && (V || n == 0), "gv_moments: NULL argument");
+    return moments_impl(V, n, D, tags, C, K, (hipStream_t)stream);
+  });
+}
+
+gv_status gv_loss_grad(int32_t C, int32_t d, int32_t D, const float* A, const float* B, const double* KQ,
+                       const double* KX, double n_pairs, double* loss, float* dA, float* dB, void* stream) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(C >= 1 && C <= 65535 && d >= 1 && d <= D && D >= 1, "gv_loss_grad: bad sizes (need 1 <= d <= D)");
+    GV_REQUIRE(A && B && KQ && KX && loss, "gv_loss_grad: NULL argument");
+    GV_REQUIRE(n_pairs > 0.0 && std::isfinite(n_pairs), "gv_loss_grad: n_pairs must be positive and finite");
+    return loss_grad_impl(C, d, D, A, B, KQ, KX, n_pairs, loss, dA, dB, (hipStream_t)stream);
   });
 }
 

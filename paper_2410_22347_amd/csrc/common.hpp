@@ -210,6 +210,10 @@ gv_status score_topk_impl(const gv_index* index, const void* qhat, const float* 
 gv_status rerank_impl(const gv_index* index, const float* Q, int64_t m, const int32_t* cand,
                       int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
 gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite);
+gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* tags, hipStream_t st);
+gv_status moments_impl(const float* V, int64_t n, int D, const uint8_t* tags, int C, double* K, hipStream_t st);
+gv_status loss_grad_impl(int C, int d, int D, const float* A, const float* B, const double* KQ, const double* KX,
+                         double n_pairs, double* loss, float* dA, float* dB, hipStream_t st);
 
 // FP64 matrix-core GEMM: C(i, j) = sum_k a(i, k) b(j, k) with operand layouts
 // described by GemmOperand; epilogue selects how C is stored.
@@ -220,6 +224,7 @@ struct GemmOperand {
   int64_t ld;
   const int64_t* gather;  // optional: RowMajor -> row index of i; KMajor -> row index of k
   Layout layout;
+  int64_t bstride = 0;    // batched products: elements between consecutive operands
 };
 enum class Epi { StoreF64, AddF64, StoreF32Proj, StoreF32 };
 struct GemmOut {
@@ -228,10 +233,14 @@ struct GemmOut {
   int cd;     // StoreF32Proj: columns per cluster (d)
   int cdp;    // StoreF32Proj: padded columns per cluster
   const int64_t* row_map;  // StoreF32: output row of i (optional)
+  int64_t bstride = 0;     // batched products: elements between consecutive outputs
+  double alpha = 1.0;      // every epilogue stores alpha * C
 };
+// batch >= 1 independent products (blockIdx.z), operands and outputs offset by
+// their bstride
 template <typename TA, typename TB>
 gv_status gemm_f64(int64_t M, int64_t N, int64_t K, GemmOperand<TA> a, GemmOperand<TB> b, Epi epi,
-                   GemmOut out, hipStream_t st);
+                   GemmOut out, hipStream_t st, int batch = 1);
 
 // host symmetric eigensolver (Householder tridiagonalisation + implicit QL/QR)
 // A: n x n symmetric (row-major, overwritten); lam: n eigenvalues decreasing;

@@ -118,29 +118,34 @@ __global__ void k_quantize(const float* __restrict__ v, int64_t n_pad, int d, in
 
 }  // namespace
 
+// tag_i = arg-max_c <x_i, mu_c> in FP64, lowest c on ties (the cluster-tag
+// equation of Section 4)
+gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* tags, hipStream_t st) {
+  const int C = model->C, D = model->D;
+  const int64_t chunk = std::min<int64_t>(n, 1 << 20);
+  double* dots = nullptr;
+  GV_HIP(hipMallocAsync((void**)&dots, sizeof(double) * chunk * C, st));
+  gv_status s = GV_OK;
+  for (int64_t s0 = 0; s0 < n && s == GV_OK; s0 += chunk) {
+    const int64_t rows = std::min(chunk, n - s0);
+    GemmOperand<float> xo{X + s0 * D, D, nullptr, Layout::RowMajor};
+    GemmOperand<double> mo{model->mu, D, nullptr, Layout::RowMajor};
+    s = gemm_f64<float, double>(rows, C, D, xo, mo, Epi::StoreF64, GemmOut{dots, C, 0, 0, nullptr}, st);
+    if (s == GV_OK)
+      hipLaunchKernelGGL(k_argmax_u8, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, dots, rows, C,
+                         tags + s0);
+  }
+  GV_HIP(hipFreeAsync(dots, st));
+  GV_TRY(s);
+  GV_HIP(hipGetLastError());
+  return GV_OK;
+}
+
 gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt, hipStream_t st, gv_index* idx) {
   const int C = model->C, d = model->d, D = model->D, dp = pad_dim(d);
 
   // ------------------------------------------------ tags, FP64 arg-max (Eq. 9)
-  {
-    const int64_t chunk = std::min<int64_t>(n, 1 << 20);
-    double* dots = nullptr;
-    GV_HIP(hipMallocAsync((void**)&dots, sizeof(double) * chunk * C, st));
-    gv_status s = GV_OK;
-    for (int64_t s0 = 0; s0 < n && s == GV_OK; s0 += chunk) {
-      int64_t rows = std::min(chunk, n - s0);
-      GemmOperand<float> xo{X + s0 * D, D, nullptr, Layout::RowMajor};
-      GemmOperand<double> mo{model->mu, D, nullptr, Layout::RowMajor};
-      s = gemm_f64<float, double>(rows, C, D, xo, mo, Epi::StoreF64, GemmOut{dots, C, 0, 0, nullptr}, st);
-      if (s == GV_OK) {
-        hipLaunchKernelGGL(k_argmax_u8, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, dots, rows, C,
-                           idx->tags + s0);
-      }
-    }
-    GV_HIP(hipFreeAsync(dots, st));
-    GV_TRY(s);
-    GV_HIP(hipGetLastError());
-  }
+  GV_TRY(tags_impl(model, X, n, idx->tags, st));
 
   // ------------------------------------------------ stable grouping by tag, padded segments
   const int64_t nb = (n + kBlockRows - 1) / kBlockRows;

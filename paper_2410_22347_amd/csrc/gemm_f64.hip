@@ -58,6 +58,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
                                                   GemmOperand<TB> b, GemmOut out) {
   __shared__ double As[TK][LDSP];
   __shared__ double Bs[TK][LDSP];
+  a.p += (int64_t)blockIdx.z * a.bstride;
+  b.p += (int64_t)blockIdx.z * b.bstride;
+  const int64_t zo = (int64_t)blockIdx.z * out.bstride;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t i0 = (int64_t)blockIdx.x * TM, j0 = (int64_t)blockIdx.y * TN;
@@ -101,17 +104,17 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
         int64_t i = i0 + wi + 16 * x + (lane >> 4) + 4 * r;
         int64_t j = j0 + wj + 16 * y + (lane & 15);
         if (i >= M || j >= N) continue;
-        double v = acc[x][y][r];
+        const double v = out.alpha * acc[x][y][r];
         if (EPI == Epi::StoreF64) {
-          ((double*)out.p)[i * out.ldc + j] = v;
+          ((double*)out.p + zo)[i * out.ldc + j] = v;
         } else if (EPI == Epi::AddF64) {
-          ((double*)out.p)[i * out.ldc + j] += v;
+          ((double*)out.p + zo)[i * out.ldc + j] += v;
         } else if (EPI == Epi::StoreF32Proj) {
           int64_t c = j / out.cd, jj = j - c * out.cd;
-          ((float*)out.p)[i * out.ldc + c * out.cdp + jj] = (float)v;
+          ((float*)out.p + zo)[i * out.ldc + c * out.cdp + jj] = (float)v;
         } else {
           int64_t row = out.row_map ? out.row_map[i] : i;
-          ((float*)out.p)[row * out.ldc + j] = (float)v;
+          ((float*)out.p + zo)[row * out.ldc + j] = (float)v;
         }
       }
 }
@@ -120,14 +123,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
 
 template <typename TA, typename TB>
 gv_status gemm_f64(int64_t M, int64_t N, int64_t K, GemmOperand<TA> a, GemmOperand<TB> b, Epi epi,
-                   GemmOut out, hipStream_t st) {
-  if (M <= 0 || N <= 0) return GV_OK;
+                   GemmOut out, hipStream_t st, int batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return GV_OK;
   int64_t gx = (M + TM - 1) / TM, gy = (N + TN - 1) / TN;
-  if (gy > 65535) {
-    set_error("gemm_f64: N too large");
+  if (gy > 65535 || batch > 65535) {
+    set_error("gemm_f64: N or batch too large");
     return GV_EINVAL;
   }
-  dim3 grid((unsigned)gx, (unsigned)gy);
+  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)batch);
   switch (epi) {
     case Epi::StoreF64:
       hipLaunchKernelGGL((k_gemm_f64<TA, TB, Epi::StoreF64>), grid, dim3(256), 0, st, M, N, K, a, b, out);
@@ -147,10 +150,12 @@ gv_status gemm_f64(int64_t M, int64_t N, int64_t K, GemmOperand<TA> a, GemmOpera
 }
 
 template gv_status gemm_f64<double, double>(int64_t, int64_t, int64_t, GemmOperand<double>,
-                                            GemmOperand<double>, Epi, GemmOut, hipStream_t);
+                                            GemmOperand<double>, Epi, GemmOut, hipStream_t, int);
 template gv_status gemm_f64<float, double>(int64_t, int64_t, int64_t, GemmOperand<float>,
-                                           GemmOperand<double>, Epi, GemmOut, hipStream_t);
+                                           GemmOperand<double>, Epi, GemmOut, hipStream_t, int);
+template gv_status gemm_f64<double, float>(int64_t, int64_t, int64_t, GemmOperand<double>,
+                                           GemmOperand<float>, Epi, GemmOut, hipStream_t, int);
 template gv_status gemm_f64<float, float>(int64_t, int64_t, int64_t, GemmOperand<float>,
-                                          GemmOperand<float>, Epi, GemmOut, hipStream_t);
+                                          GemmOperand<float>, Epi, GemmOut, hipStream_t, int);
 
 }  // namespace gv

@@ -39,6 +39,10 @@ namespace gv {
 namespace scan {
 
 constexpr int kCap = 2048;  // key slots per (query, range) list
+// Survivor keys are staged in LDS and written to the lists in batches: vector
+// stores share the memory counter with the tile loads, so a store issued in the
+// loop would make the next tile's wait also wait for the store's completion.
+constexpr int kStage = 512;
 constexpr int kRows = kTileRows;
 enum Mode { kFilter = 0, kDense = 1 };
 
@@ -123,6 +127,9 @@ struct WaveSmem {
   uint64_t idk[CAPL];  // compaction: keys ordered by (score desc, id asc)
   uint32_t row[CAPL];  //             and the stored row of each
   f32x16 acc[64];      // survivor extraction: one lane's 16 scores, indexed per lane
+  uint32_t nst;        // staged survivors
+  uint32_t spos[kStage];  // staged survivors: key slot in the list buffer
+  uint64_t skey[kStage];  //                   and the key
 };
 
 // Reduce the list L of n keys (n > keep) to its `keep` best by (score desc,
@@ -251,6 +258,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
     const int64_t q = q0 + i;
     w.tau[i] = (q < a.m) ? (a.seed ? a.seed[q] : -INFINITY) : INFINITY;
   }
+  if (lane == 0) w.nst = 0;
   wave_sync();
 
   const int64_t stride = FULL ? 1 : a.stride;  // FULL: the scan of the whole database
@@ -278,6 +286,18 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   float st[NB];      // s_c * t_{q,c} for this lane's queries (times the operand widening)
   float inv_st[NB];  // 1 / st (exact: a power of two)
   float tau_s[NB];   // thresholds in the accumulator domain
+
+  // write the staged survivors to their lists
+  auto flush = [&]() __attribute__((always_inline)) {
+    if constexpr (MODE == kFilter) {
+      wave_sync();
+      const uint32_t n = std::min<uint32_t>(w.nst, kStage);
+      for (uint32_t i = lane; i < n; i += 64) a.buf[w.spos[i]] = w.skey[i];
+      wave_sync();
+      if (lane == 0) w.nst = 0;
+      wave_sync();
+    }
+  };
 
   // --------------------------------------------------------------- epilogue
   auto epilogue = [&](f32x16 (&A)[NB], int64_t vt, int64_t real_end) __attribute__((always_inline)) {
@@ -321,16 +341,22 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           for (int i = 0; i < 16; ++i) mask |= A[nb][i] >= t ? (1u << i) : 0u;
           const int p = __builtin_popcount(mask);
           const int pp = other_half(p);  // the other lane holding this query
-          int o = cnt[nb] + (half ? pp : 0);
-          uint64_t* L = a.buf + lbase[nb];
+          int64_t o = lbase[nb] + cnt[nb] + (half ? pp : 0);  // list slot of this lane's first survivor
           w.acc[lane] = A[nb];  // scores by per-lane index go through LDS
           const float* my = reinterpret_cast<const float*>(&w.acc[lane]);
+          uint32_t sb = p ? atomicAdd(&w.nst, (uint32_t)p) : 0u;  // staging slots
           while (__ballot(mask != 0)) {  // as many rounds as the busiest lane has survivors
             if (mask) {
               const int i = __builtin_ctz(mask);
               mask &= mask - 1;
-              const float v = my[i];
-              L[o] = make_key(v * st[nb], (uint32_t)(base + (i & 3) + 8 * (i >> 2) + 4 * half));
+              const uint64_t key = make_key(my[i] * st[nb], (uint32_t)(base + (i & 3) + 8 * (i >> 2) + 4 * half));
+              if (sb < kStage) {
+                w.spos[sb] = (uint32_t)o;
+                w.skey[sb] = key;
+              } else {
+                a.buf[o] = key;  // stage full: write through
+              }
+              ++sb;
               ++o;
             }
           }
@@ -345,7 +371,12 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
     if constexpr (MODE == kFilter) {
       bool full = false;
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) { full |= cnt[decltype(nbc)::value] > lim; });
-      if (__ballot(full) == 0) return;
+      const bool stage_half = __builtin_amdgcn_readfirstlane(w.nst) > kStage / 2;
+      if (__ballot(full) == 0) {
+        if (stage_half) flush();
+        return;
+      }
+      flush();  // the lists must be complete before a compaction reads them
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
         constexpr int nb = decltype(nbc)::value;
         uint64_t fm = __ballot(cnt[nb] > lim) & 0xFFFFFFFFull;
@@ -445,6 +476,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
     }
     v = v1;
   }
+  flush();
 
   if constexpr (MODE == kFilter) {
     if (half == 0) {

@@ -99,3 +99,19 @@ def test_padded_dim():
     import paper_2410_22347_amd as gv
     assert [gv.padded_dim(d) for d in (0, 1, 16, 32, 33, 64, 100, 128, 129, 160, 161, 192, 200, 256)] == \
         [0, 32, 32, 32, 64, 64, 128, 128, 160, 160, 192, 192, 256, 256]
+
+
+def test_loss_argument_errors():
+    """Invalid sizes or pointers are rejected before any device call."""
+    import paper_2410_22347_amd as gv
+    lib = gv._lib
+    p = ctypes.c_void_p(16)  # never dereferenced: the checks fail first
+    assert lib.gv_loss_grad(0, 4, 8, p, p, p, p, 1.0, p, None, None, None) == -1
+    assert lib.gv_loss_grad(2, 9, 8, p, p, p, p, 1.0, p, None, None, None) == -1
+    assert lib.gv_loss_grad(2, 4, 8, None, p, p, p, 1.0, p, None, None, None) == -1
+    assert lib.gv_loss_grad(2, 4, 8, p, p, p, p, 0.0, p, None, None, None) == -1
+    assert lib.gv_loss_grad(2, 4, 8, p, p, p, p, float("nan"), p, None, None, None) == -1
+    assert lib.gv_moments(p, 10, 8, None, 2, p, None) == -1
+    assert lib.gv_moments(p, 10, 0, None, 1, p, None) == -1
+    assert lib.gv_moments(p, 10, 8, None, 1, None, None) == -1
+    assert lib.gv_tags(None, p, 10, p, None) == -4
