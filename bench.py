@@ -67,6 +67,10 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=32)
     ap.add_argument("--splits", type=int, default=0, help="override the row ranges per query block (0: automatic)")
     ap.add_argument("--qpw", type=int, default=0, help="override the queries per wavefront (0: automatic)")
+    ap.add_argument("--batched", action="store_true",
+                    help="the batched uneven workload instead: 64 collections (n in [1e4, 2e6], D in {256..1024}, "
+                         "d = D/4, C in {4, 16, 32}, m log-uniform in [1, 4096], bf16, kappa 100) in one graph launch")
+    ap.add_argument("--collections", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run 3 plain 1 GiB device copies before timing (counter calibration runs)")
     return ap.parse_args()
@@ -158,12 +162,83 @@ def cpu_baseline(X, geom, wl, m_s, n_s):
             "host_cpus": os.cpu_count()}
 
 
+def batched_main(a):
+    """Batched uneven collections: every collection's search as a branch of one
+    captured graph (gv_search_batched), replayed; compared with the same searches
+    issued one collection at a time.  Prints one JSON line for this workload."""
+    import torch
+    import synth
+    import paper_2410_22347_amd as gv
+    dev = torch.device("cuda:0")
+    cols = synth.batched_collections(a.collections)
+    k, kappa, fmt = 10, 100, "bf16"
+    models, indexes, Qs, keep = [], [], [], []
+    t0 = time.perf_counter()
+    for c in cols:
+        geom = synth.make_geometry(c.cfg, c.D, c.C, "mixture")
+        X = synth.draw_torch(geom, c.n, synth.S_DB, dev)
+        QL = synth.draw_torch(geom, 10_000, synth.S_QLEARN, dev, queries_=True)
+        Q = synth.draw_torch(geom, c.m, synth.S_QTEST, dev, queries_=True)
+        rows = torch.from_numpy(synth.learn_rows(c.n, synth.learn_sample_size(c.n), c.cfg)).to(dev)
+        model = gv.fit(X[rows].contiguous(), QL, c.d, c.C, seed=synth.fit_seed(c.cfg))
+        index = gv.encode(model, X, fmt)  # borrows X
+        models.append(model); indexes.append(index); Qs.append(Q); keep.append(X)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    sum_m = sum(c.m for c in cols)
+    log(f"[bench] batched: {len(cols)} collections, {sum(c.n for c in cols):,} rows, {sum_m} queries, "
+        f"built in {t_build:.1f} s")
+    out = gv.search_batched(models, indexes, Qs, k, kappa)
+    for _ in range(a.warmup):
+        gv.search_batched(models, indexes, Qs, k, kappa, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        gv.search_batched(models, indexes, Qs, k, kappa, out=out)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / a.steps
+    for _ in range(2):
+        for md, ix, Q in zip(models, indexes, Qs):
+            gv.search(md, ix, Q, k, kappa)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        for md, ix, Q in zip(models, indexes, Qs):
+            gv.search(md, ix, Q, k, kappa)
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t0) / a.steps
+    ok = all(torch.equal(o[0], gv.search(md, ix, Q, k, kappa)[0]) for o, md, ix, Q in zip(out, models, indexes, Qs))
+    # roofline of the round: streamed reduced vectors + rerank gathers vs scoring flops
+    nbytes = sum(c.n * c.d * 2 + c.m * kappa * c.D * 4 for c in cols)
+    flops = sum(2.0 * c.m * c.n * c.d + 2.0 * c.m * c.C * c.d * c.D for c in cols)
+    t_hbm, t_mfma = nbytes / (PEAK_HBM_GBS * 1e9), flops / (PEAK_TFLOPS[fmt] * 1e12)
+    t_sum = sum(max((c.n * c.d * 2 + c.m * kappa * c.D * 4) / (PEAK_HBM_GBS * 1e9),
+                    (2.0 * c.m * c.n * c.d) / (PEAK_TFLOPS[fmt] * 1e12)) for c in cols)
+    res = {"metric": "queries/s over the batched uneven collections (one graph launch per round)",
+           "value": sum_m / dt_b, "unit": "queries/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": dt_b * 1e3, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": f"batched{len(cols)}-uneven", "collections": len(cols), "queries": sum_m,
+                      "rows": sum(c.n for c in cols), "kappa": kappa, "k": k, "storage": fmt},
+           "sequential": {"value": sum_m / dt_s, "ms_per_step": dt_s * 1e3},
+           "results_equal_single_searches": bool(ok),
+           "roofline": {"bound": "hbm" if t_hbm > t_mfma else "mfma",
+                        "ideal_overlap_ms": max(t_hbm, t_mfma) * 1e3, "no_overlap_ms": t_sum * 1e3,
+                        "frac_ideal_overlap": max(t_hbm, t_mfma) / dt_b},
+           "build_s": t_build}
+    log(f"[bench] batched: {res['value']:,.0f} q/s ({dt_b * 1e3:.2f} ms per round) vs one at a time "
+        f"{res['sequential']['value']:,.0f} q/s; bound {max(t_hbm, t_mfma) * 1e3:.2f} ms")
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (this path does not shard)",
               file=sys.stderr)
         return 2
+    if a.batched:
+        return batched_main(a)
     import torch
     import synth
     import paper_2410_22347_amd as gv

@@ -209,6 +209,31 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
                     int32_t k, int32_t kappa, int32_t* out_ids, float* out_scores, void* stream);
 
 /*
+ * gv_search_batched -- Algorithm 1 for n_coll independent collections (each
+ * its own model and index, query batch and outputs), as one graph launch: every
+ * collection's S1-S4 sequence is captured as a branch of one HIP graph whose
+ * branches run concurrently on the device.  The graph, its workspace and the
+ * argument list are kept; a later call with exactly the same arguments (handles,
+ * pointers, sizes, k, kappa, stream, tuning) replays the graph without host
+ * work.  Per collection the results equal gv_search's.
+ * models, indexes, Q, m, out_ids, out_scores: host arrays of n_coll entries
+ * (out_scores may be NULL, or hold NULL entries); m[i] == 0 skips a collection.
+ * Arguments as gv_search; all indexes on the current device.
+ * Collections run on four device streams (collection i on stream i % 4); the
+ * kept workspace holds, per stream, the largest search scratch of its
+ * collections, and stays allocated until a call with other arguments, or
+ * gv_batch_release.
+ * Calls that overlap (other threads) are serialised.
+ * Errors: as gv_search; GV_EDEVICE if capture or instantiation fails.
+ */
+gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const gv_index* const* indexes,
+                            const float* const* Q, const int64_t* m, int32_t k, int32_t kappa,
+                            int32_t* const* out_ids, float* const* out_scores, void* stream);
+
+/* gv_batch_release -- free the graph and workspace kept by gv_search_batched. */
+void gv_batch_release(void);
+
+/*
  * gv_project -- stage S1 alone (Algorithm 4, preprocess).
  * Q device m x D FP32.  qc device m x C x d_pad FP32 (may be NULL): q_c,
  * zero padded, d_pad = gv_padded_dim(d).  t device m x C FP32: the scales.  qhat device m x C x d_pad

@@ -28,7 +28,7 @@ EXPORTED = [
     "gv_model_export", "gv_model_stats", "gv_model_destroy", "gv_encode", "gv_index_shape",
     "gv_index_export", "gv_index_destroy", "gv_search", "gv_project", "gv_score_topk",
     "gv_rerank", "gv_search_tuning", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
-    "gv_padded_dim", "gv_tags", "gv_moments", "gv_loss_grad",
+    "gv_padded_dim", "gv_tags", "gv_moments", "gv_loss_grad", "gv_search_batched", "gv_batch_release",
 ]
 
 
@@ -82,6 +82,8 @@ _sig("gv_padded_dim", [_i32], _i32)
 _sig("gv_host_eigh", [_i32, _vp, _vp, _vp])
 _sig("gv_profile_enable", [_i32])
 _sig("gv_tags", [_vp, _vp, _i64, _vp, _vp])
+_sig("gv_search_batched", [_i32, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp])
+_sig("gv_batch_release", [], None)
 _sig("gv_moments", [_vp, _i64, _i32, _vp, _i32, _vp, _vp])
 _sig("gv_loss_grad", [_i32, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp])
 _sig("gv_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
@@ -291,6 +293,38 @@ def profile_read():
     _check(_lib.gv_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
            "gv_profile_read")
     return a.value, b.value, c.value, d.value
+
+
+def search_batched(models, indexes, Qs, k: int, kappa: int, out=None):
+    """Algorithm 1 for several collections in one graph launch (gv_search_batched).
+    Qs: list of float32 CUDA tensors (m_i x D_i).  out: optional list of
+    (ids, scores) tensors from a previous call with the same shapes; passing them
+    back with the same query tensors replays the captured graph.
+    Returns the list of (ids, scores)."""
+    import torch
+    n = len(models)
+    if not (len(indexes) == n and len(Qs) == n):
+        raise ValueError("search_batched: models, indexes and Qs differ in length")
+    if out is None:
+        out = [(torch.empty((Q.shape[0], k), dtype=torch.int32, device=Q.device),
+                torch.empty((Q.shape[0], k), dtype=torch.float32, device=Q.device)) for Q in Qs]
+    for Q, md, (ids, sc) in zip(Qs, models, out):
+        _dev_f32(Q)
+        if Q.shape[1] != md.D or ids.shape != (Q.shape[0], k) or sc.shape != (Q.shape[0], k):
+            raise ValueError("search_batched: query or output shapes differ")
+    arr = lambda vals: (ctypes.c_void_p * n)(*vals)
+    mh = arr([md._h for md in models])
+    ih = arr([ix._h for ix in indexes])
+    qp = arr([Q.data_ptr() for Q in Qs])
+    ms = (ctypes.c_int64 * n)(*[Q.shape[0] for Q in Qs])
+    op = arr([o[0].data_ptr() for o in out])
+    sp = arr([o[1].data_ptr() for o in out])
+    _check(_lib.gv_search_batched(n, mh, ih, qp, ms, k, kappa, op, sp, _stream()), "gv_search_batched")
+    return out
+
+
+def batch_release():
+    _lib.gv_batch_release()
 
 
 def tags(model: Model, X):

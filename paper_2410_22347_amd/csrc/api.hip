@@ -32,8 +32,12 @@ bool g_prof_on = false;
 
 bool profiling() { return g_prof_on; }
 
+// set while gv_search_batched captures a graph: no profiling events then
+static thread_local bool g_capturing = false;
+bool capturing_batch() { return g_capturing; }
+
 void profile_mark(hipStream_t st, int kind, bool begin) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || capturing_batch()) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return;
@@ -445,25 +449,154 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
     if (m == 0) return GV_OK;
     GV_REQUIRE(Q && out_ids, "gv_search: NULL argument");
     hipStream_t st = (hipStream_t)stream;
-    const int C = index->C, dp = index->dp;
-    const size_t eb = fmt_bytes(index->fmt);
-    float* t = nullptr;
-    void* qhat = nullptr;
-    int32_t* cand = nullptr;
-    float* cand_sc = nullptr;
-    GV_HIP(hipMallocAsync((void**)&t, sizeof(float) * m * C, st));
-    GV_HIP(hipMallocAsync(&qhat, eb * m * C * dp, st));
-    GV_HIP(hipMallocAsync((void**)&cand, sizeof(int32_t) * m * kappa, st));
-    GV_HIP(hipMallocAsync((void**)&cand_sc, sizeof(float) * m * kappa, st));
-    gv_status s = project_impl(model, index->fmt, Q, m, nullptr, t, qhat, st);
-    if (s == GV_OK) s = score_topk_impl(index, qhat, t, m, kappa, cand, cand_sc, st);
-    if (s == GV_OK) s = rerank_impl(index, Q, m, cand, kappa, k, out_ids, out_scores, st);
-    (void)hipFreeAsync(t, st);
-    (void)hipFreeAsync(qhat, st);
-    (void)hipFreeAsync(cand, st);
-    (void)hipFreeAsync(cand_sc, st);
+    keep_pool(index->device);
+    SearchPlan plan;
+    GV_TRY(search_plan(model, index, m, kappa, &plan));
+    void* ws = nullptr;
+    GV_HIP(hipMallocAsync(&ws, plan.bytes, st));
+    const gv_status s = search_run(model, index, Q, m, k, kappa, out_ids, out_scores, plan, ws, st);
+    (void)hipFreeAsync(ws, st);
     return s;
   });
+}
+
+// ---------------------------------------------------------------------------- batched search
+namespace {
+
+// One captured batch: the graph of every collection's search, its workspace,
+// and the arguments it was captured with (a replay needs the same ones).
+struct BatchGraph {
+  std::vector<uintptr_t> key;
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+  int device = -1;
+};
+std::mutex g_batch_mu;
+BatchGraph g_batch;
+constexpr int kBatchStreams = 4;
+hipStream_t g_side[64][kBatchStreams] = {};
+hipStream_t g_origin[64] = {};  // captures start here (the caller's stream may be the legacy default stream)
+hipEvent_t g_fork[64] = {}, g_join[64][kBatchStreams] = {};
+void release_batch(BatchGraph& b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.ws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b.ws);
+  }
+  b = BatchGraph{};
+}
+
+gv_status side_streams(int dev) {
+  if (dev < 0 || dev >= 64) {
+    set_error("device index out of range");
+    return GV_EDEVICE;
+  }
+  if (g_fork[dev]) return GV_OK;
+  for (int j = 0; j < kBatchStreams; ++j) {
+    GV_HIP(hipStreamCreateWithFlags(&g_side[dev][j], hipStreamNonBlocking));
+    GV_HIP(hipEventCreateWithFlags(&g_join[dev][j], hipEventDisableTiming));
+  }
+  GV_HIP(hipStreamCreateWithFlags(&g_origin[dev], hipStreamNonBlocking));
+  GV_HIP(hipEventCreateWithFlags(&g_fork[dev], hipEventDisableTiming));
+  return GV_OK;
+}
+
+}  // namespace
+
+gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const gv_index* const* indexes,
+                            const float* const* Q, const int64_t* m, int32_t k, int32_t kappa,
+                            int32_t* const* out_ids, float* const* out_scores, void* stream) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(n_coll >= 0, "gv_search_batched: n_coll < 0");
+    if (n_coll == 0) return GV_OK;
+    GV_REQUIRE(models && indexes && Q && m && out_ids, "gv_search_batched: NULL argument");
+    int dev = 0;
+    GV_HIP(hipGetDevice(&dev));
+    std::vector<SearchPlan> plans(n_coll);
+    // collection i runs on side stream i % kBatchStreams; collections on one
+    // stream run one after the other and share that stream's workspace slot
+    std::vector<size_t> slot(kBatchStreams, 0);
+    std::vector<uintptr_t> key{(uintptr_t)n_coll, (uintptr_t)k, (uintptr_t)kappa, (uintptr_t)stream, (uintptr_t)dev,
+                               (uintptr_t)tuned_splits(), (uintptr_t)tuned_qpw(), (uintptr_t)tuned_cap()};
+    for (int i = 0; i < n_coll; ++i) {
+      const gv_model* md = models[i];
+      const gv_index* ix = indexes[i];
+      if (!valid(md) || !valid(ix)) return GV_ENOTFIT;
+      GV_REQUIRE(md->C == ix->C && md->d == ix->d && md->D == ix->D, "gv_search_batched: model and index shapes differ");
+      GV_REQUIRE(ix->device == dev, "gv_search_batched: index on another device");
+      GV_TRY(check_search_args(ix, m[i], k, kappa));
+      GV_REQUIRE(m[i] == 0 || (Q[i] && out_ids[i]), "gv_search_batched: NULL query or output");
+      if (m[i] > 0) GV_TRY(search_plan(md, ix, m[i], kappa, &plans[i]));
+      if (m[i] > 0) slot[i % kBatchStreams] = std::max(slot[i % kBatchStreams], (plans[i].bytes + 255) / 256 * 256);
+      for (uintptr_t v : {(uintptr_t)md, (uintptr_t)ix, (uintptr_t)Q[i], (uintptr_t)m[i], (uintptr_t)out_ids[i],
+                          (uintptr_t)(out_scores ? out_scores[i] : nullptr)})
+        key.push_back(v);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (g_batch.exec && g_batch.key == key) {  // same batch as last time: replay
+      GV_HIP(hipGraphLaunch(g_batch.exec, st));
+      return GV_OK;
+    }
+    release_batch(g_batch);
+    GV_TRY(side_streams(dev));
+    std::vector<size_t> off(kBatchStreams + 1, 0);
+    for (int j = 0; j < kBatchStreams; ++j) off[j + 1] = off[j] + slot[j];
+    void* ws = nullptr;
+    GV_HIP(hipMalloc(&ws, std::max<size_t>(off[kBatchStreams], 256)));
+    // capture every collection's search as a branch of one graph
+    gv_status s = GV_OK;
+    hipGraph_t graph = nullptr;
+    hipStream_t org = g_origin[dev];
+    if (hipStreamBeginCapture(org, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipFree(ws);
+      set_error("gv_search_batched: stream capture failed to start");
+      return GV_EDEVICE;
+    }
+    g_capturing = true;
+    hipError_t e = hipEventRecord(g_fork[dev], org);
+    for (int j = 0; j < kBatchStreams && e == hipSuccess; ++j) e = hipStreamWaitEvent(g_side[dev][j], g_fork[dev], 0);
+    if (e != hipSuccess) s = GV_EDEVICE;
+    for (int i = 0; i < n_coll && s == GV_OK; ++i) {
+      if (m[i] == 0) continue;
+      const int j = i % kBatchStreams;
+      s = search_run(models[i], indexes[i], Q[i], m[i], k, kappa, out_ids[i], out_scores ? out_scores[i] : nullptr,
+                     plans[i], (uint8_t*)ws + off[j], g_side[dev][j]);
+    }
+    for (int j = 0; j < kBatchStreams; ++j) {
+      if (hipEventRecord(g_join[dev][j], g_side[dev][j]) != hipSuccess ||
+          hipStreamWaitEvent(org, g_join[dev][j], 0) != hipSuccess)
+        s = s == GV_OK ? GV_EDEVICE : s;
+    }
+    g_capturing = false;
+    const hipError_t ec = hipStreamEndCapture(org, &graph);
+    if (s == GV_OK && ec != hipSuccess) {
+      set_error(std::string("gv_search_batched: capture failed: ") + hipGetErrorString(ec));
+      s = GV_EDEVICE;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (s == GV_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      set_error("gv_search_batched: graph instantiation failed");
+      s = GV_EDEVICE;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (s != GV_OK) {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      (void)hipFree(ws);
+      return s;
+    }
+    g_batch.key = std::move(key);
+    g_batch.exec = exec;
+    g_batch.ws = ws;
+    g_batch.device = dev;
+    GV_HIP(hipGraphLaunch(exec, st));
+    return GV_OK;
+  });
+}
+
+void gv_batch_release(void) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  release_batch(g_batch);
 }
 
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap) {

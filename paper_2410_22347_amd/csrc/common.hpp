@@ -207,6 +207,14 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
                        float* t, void* qhat, hipStream_t st);
 gv_status score_topk_impl(const gv_index* index, const void* qhat, const float* t, int64_t m,
                           int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st);
+void keep_pool(int device);
+// one search's scratch, carved from a single workspace (byte offsets)
+struct SearchPlan {
+  size_t off_t = 0, off_qc = 0, off_qhat = 0, off_cand = 0, off_csc = 0, off_scan = 0, bytes = 0;
+};
+gv_status search_plan(const gv_model* model, const gv_index* index, int64_t m, int kappa, SearchPlan* plan);
+gv_status search_run(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int k, int kappa,
+                     int32_t* out_ids, float* out_scores, const SearchPlan& plan, void* workspace, hipStream_t st);
 gv_status rerank_impl(const gv_index* index, const float* Q, int64_t m, const int32_t* cand,
                       int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
 gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite);
@@ -252,6 +260,7 @@ int tuned_qpw();
 int tuned_cap();
 
 // benchmark hooks: events around scoring (kind 0) and merge (kind 1) launches
+// (off while a batched search is being captured into a graph)
 bool profiling();
 void profile_mark(hipStream_t st, int kind, bool begin);
 }  // namespace gv

@@ -311,6 +311,8 @@ std::vector<int64_t> cascade(int64_t n, int kappa) {
   return s;
 }
 
+}  // namespace
+
 // freed search scratch stays in the stream-ordered pool between calls
 void keep_pool(int dev) {
   static bool done[64] = {};
@@ -323,53 +325,65 @@ void keep_pool(int dev) {
   done[dev] = true;
 }
 
-}  // namespace
-
 // smallest list capacity the scan accepts for a given kappa: a list is checked
 // for overflow every 2P + 1 tiles (P <= 6) and takes at most 32 keys per tile
 int min_list_cap(int kappa) { return kappa + kRows * 13 + 1; }
 
-gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t, int64_t m, int kappa,
-                          int32_t* cand_ids, float* cand_scores, hipStream_t st) {
-  if (m == 0) return GV_OK;
-  keep_pool(idx->device);
-  const int fmt = idx->fmt;
-  const int cap = tuned_cap() > 0 ? tuned_cap() : kCap;
-  if (cap < min_list_cap(kappa) || cap > kCap) {
+namespace {
+
+// Launch plan of S2/S3 for one (index, m, kappa): cascade levels, their
+// shapes, and the scratch they need.
+struct ScanPlan {
+  std::vector<int64_t> levels;
+  std::vector<Shape> shapes;
+  bool has_dense = false;
+  int Rmax = 1;
+  int64_t ns = 0;
+  int cap = kCap;
+  size_t off_buf = 0, off_cnt = 0, off_seed = 0, off_dense = 0, bytes = 0;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p) {
+  p->cap = tuned_cap() > 0 ? tuned_cap() : kCap;
+  if (p->cap < min_list_cap(kappa) || p->cap > kCap) {
     set_error("candidate list capacity must lie in [kappa + 417, 2048]");
     return GV_EINVAL;
   }
-  const std::vector<int64_t> levels = cascade(idx->n, kappa);
-  const bool has_dense = levels.size() > 1;
+  p->levels = cascade(idx->n, kappa);
+  p->has_dense = p->levels.size() > 1;
   const int64_t ntiles = idx->n_pad / kRows;
-
-  std::vector<Shape> shapes;
-  int Rmax = 1;
-  for (size_t li = 0; li < levels.size(); ++li) {
-    const int64_t s = levels[li];
-    const Shape sh = choose_shape(fmt, idx->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
-    if (!(has_dense && li == 0)) Rmax = std::max(Rmax, sh.R);  // the dense scan writes no lists
-    shapes.push_back(sh);
+  p->shapes.clear();
+  p->Rmax = 1;
+  for (size_t li = 0; li < p->levels.size(); ++li) {
+    const int64_t s = p->levels[li];
+    const Shape sh = choose_shape(idx->fmt, idx->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
+    if (!(p->has_dense && li == 0)) p->Rmax = std::max(p->Rmax, sh.R);  // the dense scan writes no lists
+    p->shapes.push_back(sh);
   }
-  const int64_t ns = has_dense ? ((ntiles + levels[0] - 1) / levels[0]) * kRows : 0;
-
-  uint64_t* buf = nullptr;
-  int32_t* cnt = nullptr;
-  float* seed = nullptr;
-  float* dense = nullptr;
-  gv_status s = GV_OK;
-  auto alloc = [&](void** p, size_t bytes) {
-    if (s == GV_OK && hipMallocAsync(p, std::max<size_t>(bytes, 8), st) != hipSuccess) {
-      set_error("search scratch allocation failed");
-      s = GV_ENOMEM;
-    }
-  };
-  alloc((void**)&buf, sizeof(uint64_t) * m * Rmax * cap);
-  alloc((void**)&cnt, sizeof(int32_t) * m * Rmax);
-  if (has_dense) {
-    alloc((void**)&seed, sizeof(float) * m);
-    alloc((void**)&dense, sizeof(float) * m * ns);
+  p->ns = p->has_dense ? ((ntiles + p->levels[0] - 1) / p->levels[0]) * kRows : 0;
+  const uint64_t keys = (uint64_t)m * p->Rmax * p->cap;
+  if (keys >= (1ull << 32)) {  // list slots are staged as 32-bit indices
+    set_error("search batch too large for the candidate lists (reduce m)");
+    return GV_EUNSUPPORTED;
   }
+  size_t o = 0;
+  p->off_buf = o;   o = align256(o + sizeof(uint64_t) * keys);
+  p->off_cnt = o;   o = align256(o + sizeof(int32_t) * m * p->Rmax);
+  p->off_seed = o;  o = align256(o + (p->has_dense ? sizeof(float) * m : 0));
+  p->off_dense = o; o = align256(o + (p->has_dense ? sizeof(float) * m * p->ns : 0));
+  p->bytes = o;
+  return GV_OK;
+}
+
+gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const void* qhat, const float* t, int64_t m,
+                   int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st) {
+  uint64_t* buf = (uint64_t*)(ws + p.off_buf);
+  int32_t* cnt = (int32_t*)(ws + p.off_cnt);
+  float* seed = p.has_dense ? (float*)(ws + p.off_seed) : nullptr;
+  float* dense = p.has_dense ? (float*)(ws + p.off_dense) : nullptr;
+  const int fmt = idx->fmt;
 
   ScoreArgs args{};
   args.xlow = (const uint8_t*)idx->xlow;
@@ -387,28 +401,28 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
   args.C = idx->C;
   args.dp = idx->dp;
   args.kappa = kappa;
-  args.cap = cap;
+  args.cap = p.cap;
 
-  if (s == GV_OK && has_dense)
-    hipLaunchKernelGGL(k_seed_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, seed);
-  for (size_t li = 0; li < levels.size() && s == GV_OK; ++li) {
-    const Shape& sh = shapes[li];
-    const bool last = li + 1 == levels.size();
+  gv_status s = GV_OK;
+  if (p.has_dense) hipLaunchKernelGGL(k_seed_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, seed);
+  for (size_t li = 0; li < p.levels.size() && s == GV_OK; ++li) {
+    const Shape& sh = p.shapes[li];
+    const bool last = li + 1 == p.levels.size();
     args.seed = li == 0 ? nullptr : seed;
     args.R = sh.R;
     args.nqb = (int)sh.nqb;
-    args.stride = (int)levels[li];
+    args.stride = (int)p.levels[li];
     args.xcd_map = sh.xcd_map;
-    if (has_dense && li == 0) {
+    if (p.has_dense && li == 0) {
       s = dispatch_fmt<kDense>(fmt, idx->dp, sh, args, st);
       if (s == GV_OK)
-        hipLaunchKernelGGL(k_dense_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, dense, m, ns, kappa, seed);
+        hipLaunchKernelGGL(k_dense_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, dense, m, p.ns, kappa,
+                           seed);
       continue;
     }
-    if (sh.R > Rmax) {  // scratch must cover every list the launch writes
+    if (sh.R > p.Rmax) {  // scratch must cover every list the launch writes
       set_error("internal: candidate scratch smaller than the launch");
-      s = GV_EDEVICE;
-      break;
+      return GV_EDEVICE;
     }
     if (last) profile_mark(st, 0, true);
     s = dispatch_fmt<kFilter>(fmt, idx->dp, sh, args, st);
@@ -416,18 +430,70 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
     if (s != GV_OK) break;
     if (last) {
       profile_mark(st, 1, true);
-      hipLaunchKernelGGL(k_select<true>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, cap, kappa, idx->ids,
+      hipLaunchKernelGGL(k_select<true>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, p.cap, kappa, idx->ids,
                          seed, cand_ids, cand_scores);
       profile_mark(st, 1, false);
     } else {
-      hipLaunchKernelGGL(k_select<false>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, cap, kappa, idx->ids,
-                         seed, (int32_t*)nullptr, (float*)nullptr);
+      hipLaunchKernelGGL(k_select<false>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, p.cap, kappa,
+                         idx->ids, seed, (int32_t*)nullptr, (float*)nullptr);
     }
   }
-  for (void* p : {(void*)buf, (void*)cnt, (void*)seed, (void*)dense})
-    if (p) (void)hipFreeAsync(p, st);
   GV_TRY(s);
   GV_HIP(hipGetLastError());
+  return GV_OK;
+}
+
+}  // namespace
+
+gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t, int64_t m, int kappa,
+                          int32_t* cand_ids, float* cand_scores, hipStream_t st) {
+  if (m == 0) return GV_OK;
+  keep_pool(idx->device);
+  ScanPlan p;
+  GV_TRY(plan_scan(idx, m, kappa, &p));
+  uint8_t* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, std::max<size_t>(p.bytes, 256), st) != hipSuccess) {
+    set_error("search scratch allocation failed");
+    return GV_ENOMEM;
+  }
+  const gv_status s = run_scan(idx, p, ws, qhat, t, m, kappa, cand_ids, cand_scores, st);
+  (void)hipFreeAsync(ws, st);
+  return s;
+}
+
+// ---------------------------------------------------------------------------- whole search
+// Scratch of one search (S1 views and scales, S2/S3 lists, candidates), carved
+// from one workspace so the sequence runs without allocations.
+gv_status search_plan(const gv_model* model, const gv_index* idx, int64_t m, int kappa, SearchPlan* sp) {
+  ScanPlan p;
+  GV_TRY(plan_scan(idx, m, kappa, &p));
+  const size_t C = idx->C, dp = idx->dp, eb = fmt_bytes(idx->fmt);
+  size_t o = 0;
+  sp->off_t = o;    o = align256(o + sizeof(float) * m * C);
+  sp->off_qc = o;   o = align256(o + sizeof(float) * m * C * dp);
+  sp->off_qhat = o; o = align256(o + eb * m * C * dp);
+  sp->off_cand = o; o = align256(o + sizeof(int32_t) * m * kappa);
+  sp->off_csc = o;  o = align256(o + sizeof(float) * m * kappa);
+  sp->off_scan = o; o = align256(o + p.bytes);
+  sp->bytes = std::max<size_t>(o, 256);
+  (void)model;
+  return GV_OK;
+}
+
+gv_status search_run(const gv_model* model, const gv_index* idx, const float* Q, int64_t m, int k, int kappa,
+                     int32_t* out_ids, float* out_scores, const SearchPlan& sp, void* workspace, hipStream_t st) {
+  if (m == 0) return GV_OK;
+  uint8_t* ws = (uint8_t*)workspace;
+  ScanPlan p;
+  GV_TRY(plan_scan(idx, m, kappa, &p));
+  float* t = (float*)(ws + sp.off_t);
+  float* qc = (float*)(ws + sp.off_qc);
+  void* qhat = ws + sp.off_qhat;
+  int32_t* cand = (int32_t*)(ws + sp.off_cand);
+  float* csc = (float*)(ws + sp.off_csc);
+  GV_TRY(project_impl(model, idx->fmt, Q, m, qc, t, qhat, st));
+  GV_TRY(run_scan(idx, p, ws + sp.off_scan, qhat, t, m, kappa, cand, csc, st));
+  GV_TRY(rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st));
   return GV_OK;
 }
 

@@ -210,3 +210,28 @@ def fit_seed(cfg: int) -> int:
 def is_pow2(v: int) -> bool:
     return v > 0 and (v & (v - 1)) == 0
 
+
+# ------------------------------------------------------------------ batched collections
+@dataclasses.dataclass
+class Collection:
+    cfg: int      # seed domain of this collection's geometry and draws
+    n: int
+    D: int
+    d: int
+    C: int
+    m: int
+
+
+def batched_collections(count: int = 64, n_lo: int = 10_000, n_hi: int = 2_000_000, m_hi: int = 4096,
+                        dims=(256, 512, 768, 1024), clusters=(4, 16, 32), cfg: int = 4):
+    """Uneven collections: n uniform in [n_lo, n_hi], D from dims, d = D/4, C from
+    clusters (mixture law with J = C), query batches log-uniform in [1, m_hi]."""
+    rng = rng_for(cfg, S_GEOM)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        D = int(rng.choice(dims))
+        C = int(rng.choice(clusters))
+        m = int(min(m_hi, max(1, round(float(np.exp(rng.uniform(0.0, np.log(m_hi))))))))
+        out.append(Collection(1000 * cfg + i, n, D, D // 4, C, m))
+    return out
