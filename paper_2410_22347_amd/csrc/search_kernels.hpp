@@ -7,6 +7,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "lds_tile.hpp"
 #include "search_common.hpp"
 
 namespace gv {
@@ -39,10 +40,6 @@ namespace gv {
 namespace scan {
 
 constexpr int kCap = 2048;  // key slots per (query, range) list
-// Survivor keys are staged in LDS and written to the lists in batches: vector
-// stores share the memory counter with the tile loads, so a store issued in the
-// loop would make the next tile's wait also wait for the store's completion.
-constexpr int kStage = 512;
 constexpr int kRows = kTileRows;
 enum Mode { kFilter = 0, kDense = 1 };
 
@@ -127,9 +124,6 @@ struct WaveSmem {
   uint64_t idk[CAPL];  // compaction: keys ordered by (score desc, id asc)
   uint32_t row[CAPL];  //             and the stored row of each
   f32x16 acc[64];      // survivor extraction: one lane's 16 scores, indexed per lane
-  uint32_t nst;        // staged survivors
-  uint32_t spos[kStage];  // staged survivors: key slot in the list buffer
-  uint64_t skey[kStage];  //                   and the key
 };
 
 // Reduce the list L of n keys (n > keep) to its `keep` best by (score desc,
@@ -183,6 +177,22 @@ __device__ inline float uniformf(float v) {
   return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
 }
 
+// s_waitcnt vmcnt(N): at most N vector memory operations of this wavefront
+// still outstanding (gfx9 encoding; expcnt and lgkmcnt not waited for)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// workgroup barrier without a memory fence: the compiler keeps memory
+// operations on their side of it, the hardware adds no waits
+__device__ __forceinline__ void block_barrier() {
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
 // compile-time unrolled loop: f(std::integral_constant<int, i>) for i in [I, N)
 template <int I, int N>
 struct Unroll {
@@ -214,16 +224,23 @@ __device__ inline float max16(const f32x16& v) {
 // output layout: rows (i % 4) + 8 * (i / 4) + 4 * h, column = lane % 32)
 __device__ constexpr int acc_row(int i, int h) { return (i & 3) + 8 * (i >> 2) + 4 * h; }
 
-template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC, bool FULL>
+template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC, bool FULL, bool WGT, int PL>
 __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   using Op = MfmaOp<FMT>;
   using S = typename Op::S;
   using T = typename Op::T;
-  constexpr int QW = 32 * NB;        // queries per wavefront
-  constexpr int U = DEFER ? 2 * P : P;  // unrolled steps per loop iteration (ring x accumulator parity)
+  constexpr int QW = 32 * NB;  // queries per wavefront
+  // unrolled steps per loop iteration (ring x accumulator parity); the
+  // workgroup-shared ring (WGT) advances one tile per step with the filter deferred
+  constexpr int U = WGT ? 2 : (DEFER ? 2 * P : P);
+  constexpr int kblock_c = 64 * Op::EPL * Op::EB;  // bytes of one k-step block of a tile
+  constexpr int TB = KS * kblock_c;                 // bytes of one tile
 
-  constexpr int CAPL = OCC >= 2 ? kCap / 2 : kCap;  // two workgroups per CU need the smaller staging
+  // two workgroups per CU, or an LDS tile ring, need the smaller compaction staging
+  constexpr int CAPL = (OCC >= 2 || WGT) ? kCap / 2 : kCap;
+  static_assert(CAPL - kRows * (U + 1) >= 256 + kRows, "the staging must hold kappa <= 256 plus a tile");
   __shared__ WaveSmem<QW, CAPL> s_wave[4];
+  __shared__ __attribute__((aligned(16))) uint8_t s_ring[WGT ? PL * TB : 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
   WaveSmem<QW, CAPL>& w = s_wave[wave];
@@ -251,14 +268,15 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
       r = rr;
     }
   }
-  if (qb >= a.nqb) return;  // padding work item of the last query group
+  // padding work item of the last query group (with a shared tile ring it still
+  // loads its share of the tiles and meets every barrier; its queries are void)
+  if (!WGT && qb >= a.nqb) return;
   const int64_t q0 = (int64_t)qb * QW;
 
   for (int i = lane; i < QW; i += 64) {
     const int64_t q = q0 + i;
     w.tau[i] = (q < a.m) ? (a.seed ? a.seed[q] : -INFINITY) : INFINITY;
   }
-  if (lane == 0) w.nst = 0;
   wave_sync();
 
   const int64_t stride = FULL ? 1 : a.stride;  // FULL: the scan of the whole database
@@ -266,8 +284,10 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   const int64_t nvirt = (ntiles + stride - 1) / stride;
   const int64_t v_begin = nvirt * r / a.R, v_end = nvirt * (r + 1) / a.R;
   const int64_t ns = nvirt * kRows;  // dense: row count of the sample
-  // a list takes at most 32 keys per tile; between two overflow checks at most U + 1 tiles
-  const int lim = a.cap - kRows * (U + 1);
+  // a list takes at most 32 keys per tile; between two overflow checks at most
+  // U + 1 tiles; a compaction stages the whole list in this wavefront's LDS,
+  // which holds CAPL keys (fewer than the list capacity with an LDS tile ring)
+  const int lim = (a.cap < CAPL ? a.cap : CAPL) - kRows * (U + 1);
 
   int cnt[NB];
   int64_t lbase[NB];  // first key slot of this lane's (query, range) list
@@ -286,18 +306,6 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   float st[NB];      // s_c * t_{q,c} for this lane's queries (times the operand widening)
   float inv_st[NB];  // 1 / st (exact: a power of two)
   float tau_s[NB];   // thresholds in the accumulator domain
-
-  // write the staged survivors to their lists
-  auto flush = [&]() __attribute__((always_inline)) {
-    if constexpr (MODE == kFilter) {
-      wave_sync();
-      const uint32_t n = std::min<uint32_t>(w.nst, kStage);
-      for (uint32_t i = lane; i < n; i += 64) a.buf[w.spos[i]] = w.skey[i];
-      wave_sync();
-      if (lane == 0) w.nst = 0;
-      wave_sync();
-    }
-  };
 
   // --------------------------------------------------------------- epilogue
   auto epilogue = [&](f32x16 (&A)[NB], int64_t vt, int64_t real_end) __attribute__((always_inline)) {
@@ -342,21 +350,14 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           const int p = __builtin_popcount(mask);
           const int pp = other_half(p);  // the other lane holding this query
           int64_t o = lbase[nb] + cnt[nb] + (half ? pp : 0);  // list slot of this lane's first survivor
-          w.acc[lane] = A[nb];  // scores by per-lane index go through LDS
-          const float* my = reinterpret_cast<const float*>(&w.acc[lane]);
-          uint32_t sb = p ? atomicAdd(&w.nst, (uint32_t)p) : 0u;  // staging slots
+          // scores by per-lane index go through LDS
+          const uint32_t my = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) f32x16*)&w.acc[lane]);
+          lds_put16(my, A[nb]);
           while (__ballot(mask != 0)) {  // as many rounds as the busiest lane has survivors
             if (mask) {
               const int i = __builtin_ctz(mask);
               mask &= mask - 1;
-              const uint64_t key = make_key(my[i] * st[nb], (uint32_t)(base + (i & 3) + 8 * (i >> 2) + 4 * half));
-              if (sb < kStage) {
-                w.spos[sb] = (uint32_t)o;
-                w.skey[sb] = key;
-              } else {
-                a.buf[o] = key;  // stage full: write through
-              }
-              ++sb;
+              a.buf[o] = make_key(lds_get(my + 4 * i) * st[nb], (uint32_t)(base + (i & 3) + 8 * (i >> 2) + 4 * half));
               ++o;
             }
           }
@@ -371,12 +372,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
     if constexpr (MODE == kFilter) {
       bool full = false;
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) { full |= cnt[decltype(nbc)::value] > lim; });
-      const bool stage_half = __builtin_amdgcn_readfirstlane(w.nst) > kStage / 2;
-      if (__ballot(full) == 0) {
-        if (stage_half) flush();
-        return;
-      }
-      flush();  // the lists must be complete before a compaction reads them
+      if (__ballot(full) == 0) return;
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
         constexpr int nb = decltype(nbc)::value;
         uint64_t fm = __ballot(cnt[nb] > lim) & 0xFFFFFFFFull;
@@ -443,40 +439,97 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
       }
     };
 
-    S ring[P][KS];
-    Unroll<0, P - 1>::run([&](auto pc) __attribute__((always_inline)) { load_tile(ring[decltype(pc)::value], v0 + decltype(pc)::value); });
-    f32x16 acc0[NB], acc1[NB];
-
-    for (int64_t vb = v0; vb < v1; vb += U) {
-      // Loads and matrix-core steps run unconditionally (tiles past the
-      // segment re-read its last tile and are not filtered), so the memory
-      // counter waits are the same on every path through the loop.
-      Unroll<0, U>::run([&](auto uc) __attribute__((always_inline)) {
-        constexpr int u = decltype(uc)::value;
-        const int64_t vt = vb + u;
-        load_tile(ring[(u + P - 1) % P], vt + P - 1);
-        if constexpr (DEFER) {
-          // matrix core on tile vt, filter of tile vt - 1
-          if constexpr (u & 1) mma_tile(ring[u % P], acc1); else mma_tile(ring[u % P], acc0);
-          if ((u > 0 || vt > v0) && vt - 1 < v1) {
+    if constexpr (WGT) {
+      // ---- tiles shared by the workgroup through an LDS ring of PL tiles.  Each
+      // wavefront copies every fourth 1 KiB chunk of a tile straight to LDS;
+      // after its own copies land (memory counter) and a barrier, every
+      // wavefront reads the whole tile from LDS.  Vector memory operations
+      // complete in order, so the wait counts the copies issued after this
+      // tile's, whatever stores happen in between.
+      static_assert(TB % 1024 == 0, "tiles are copied in 1 KiB chunks");
+      constexpr int NCH = TB / 1024;
+      constexpr int SH_HI = (NCH + 3) / 4, SH_LO = NCH / 4;
+      const bool hi = wave < (NCH & 3);
+      // LDS byte address of this lane's operands in ring slot 0
+      const uint32_t ring_lds =
+          (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t*)s_ring) + lane * Op::EPL * Op::EB;
+      int slot_in = 0;  // ring slot of the next tile to copy
+      auto issue = [&](int64_t vv) __attribute__((always_inline)) {
+        const int64_t vc = vv < v1 ? vv : v1 - 1;
+        const uint8_t* g = a.xlow + vc * stride * tile_bytes + (int64_t)lane * 16;
+        uint8_t* ls = s_ring + slot_in * TB;
+#pragma unroll
+        for (int j = wave; j < NCH; j += 4)
+          __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + j * 1024),
+                                           (__attribute__((address_space(3))) void*)(ls + j * 1024), 16, 0, 0);
+        slot_in = slot_in + 1 == PL ? 0 : slot_in + 1;
+      };
+      auto arrive = [&]() __attribute__((always_inline)) {
+        if (hi) wait_vm<(PL - 2) * SH_HI>(); else wait_vm<(PL - 2) * SH_LO>();
+        block_barrier();
+      };
+      Unroll<0, PL - 1>::run([&](auto pc) __attribute__((always_inline)) { issue(v0 + decltype(pc)::value); });
+      f32x16 acc0[NB], acc1[NB];
+      S cur[KS];
+      int slot_rd = 0;  // ring slot of the tile to score
+      for (int64_t vb = v0; vb < v1; vb += 2) {
+        Unroll<0, 2>::run([&](auto uc) __attribute__((always_inline)) {
+          constexpr int u = decltype(uc)::value;
+          const int64_t vt = vb + u;
+          if (vt >= v1) return;
+          arrive();
+          // the whole tile into registers first (one wait inside the read),
+          // then the next copy into the slot of tile vt - 1, which every
+          // wavefront finished reading before the barrier
+          LdsTile<KS, Op::EPL * Op::EB>::read(cur, ring_lds + slot_rd * TB);
+          slot_rd = slot_rd + 1 == PL ? 0 : slot_rd + 1;
+          issue(vt + PL - 1);
+          if constexpr (u & 1) mma_tile(cur, acc1); else mma_tile(cur, acc0);
+          if (vt > v0) {
             if constexpr (u & 1) epilogue(acc0, vt - 1, real_end); else epilogue(acc1, vt - 1, real_end);
           }
-        } else {
-          mma_tile(ring[u % P], acc0);
-          if (vt < v1) epilogue(acc0, vt, real_end);
-        }
-      });
-      check_overflow();
-    }
-    if constexpr (DEFER) {  // the last tile's filter, when the final step scored a real tile
-      if ((v1 - v0) % U == 0) {
-        epilogue(acc1, v1 - 1, real_end);  // U is even: the final step used acc1
+        });
         check_overflow();
+      }
+      if ((v1 - 1 - v0) & 1) epilogue(acc1, v1 - 1, real_end); else epilogue(acc0, v1 - 1, real_end);
+      check_overflow();
+      wait_vm<0>();  // the tail copies land before the ring is reused
+      block_barrier();
+    } else {
+      S ring[P][KS];
+      Unroll<0, P - 1>::run([&](auto pc) __attribute__((always_inline)) { load_tile(ring[decltype(pc)::value], v0 + decltype(pc)::value); });
+      f32x16 acc0[NB], acc1[NB];
+  
+      for (int64_t vb = v0; vb < v1; vb += U) {
+        // Loads and matrix-core steps run unconditionally (tiles past the
+        // segment re-read its last tile and are not filtered), so the memory
+        // counter waits are the same on every path through the loop.
+        Unroll<0, U>::run([&](auto uc) __attribute__((always_inline)) {
+          constexpr int u = decltype(uc)::value;
+          const int64_t vt = vb + u;
+          load_tile(ring[(u + P - 1) % P], vt + P - 1);
+          if constexpr (DEFER) {
+            // matrix core on tile vt, filter of tile vt - 1
+            if constexpr (u & 1) mma_tile(ring[u % P], acc1); else mma_tile(ring[u % P], acc0);
+            if ((u > 0 || vt > v0) && vt - 1 < v1) {
+              if constexpr (u & 1) epilogue(acc0, vt - 1, real_end); else epilogue(acc1, vt - 1, real_end);
+            }
+          } else {
+            mma_tile(ring[u % P], acc0);
+            if (vt < v1) epilogue(acc0, vt, real_end);
+          }
+        });
+        check_overflow();
+      }
+      if constexpr (DEFER) {  // the last tile's filter, when the final step scored a real tile
+        if ((v1 - v0) % U == 0) {
+          epilogue(acc1, v1 - 1, real_end);  // U is even: the final step used acc1
+          check_overflow();
+        }
       }
     }
     v = v1;
   }
-  flush();
 
   if constexpr (MODE == kFilter) {
     if (half == 0) {
@@ -517,14 +570,27 @@ struct Shape {
   int xcd_map;
 };
 
+// Query blocks that share rows (SHARED = false) take the tiles through an LDS
+// ring shared by the workgroup: one fetch per workgroup instead of one per
+// wavefront.  Tiles above 16 KiB (FP32 rows) keep per-wavefront register rings.
+template <int FMT, int KS>
+struct RingCfg {
+  static constexpr int TB = KS * 64 * MfmaOp<FMT>::EPL * MfmaOp<FMT>::EB;
+  static constexpr bool ok = FMT != GV_FP32 && TB <= 16384;
+  static constexpr int PL = TB <= 10240 ? 5 : 4;
+};
+
 template <int FMT, int KS, int NB, bool SHARED, int MODE>
 void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   using Cfg = ScanCfg<FMT, KS, NB>;
+  constexpr bool W = !SHARED && RingCfg<FMT, KS>::ok;
+  constexpr int PL = W ? RingCfg<FMT, KS>::PL : 1;
+  constexpr bool DEF = W || Cfg::defer;
   if (MODE == kFilter && args.stride == 1)
-    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, Cfg::defer, 1, true>), dim3(sh.grid), dim3(256), 0, st,
-                       args);
+    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, DEF, 1, true, W, PL>), dim3(sh.grid), dim3(256), 0,
+                       st, args);
   else
-    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, Cfg::defer, 1, false>), dim3(sh.grid), dim3(256), 0,
+    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, DEF, 1, false, W, PL>), dim3(sh.grid), dim3(256), 0,
                        st, args);
 }
 

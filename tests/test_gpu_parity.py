@@ -339,6 +339,38 @@ def test_deterministic_repeat(gv):
     assert torch.equal(c1, c2) and torch.equal(d1, d2)
 
 
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp8"])
+def test_long_lists_tile_ring(gv, fmt):
+    """Many queries (four query blocks of a workgroup share each row tile through
+    an LDS ring) and one row range per query at the default list capacity: every
+    list collects all the survivors of its query and is compacted many times from
+    lengths at the limit of the wavefront's LDS staging.  Two of the four
+    wavefronts hold no queries (padding blocks) and still take part in the ring."""
+    m = 130
+    _say(f"[long lists] {fmt} m{m}")
+    X, Q, om, oi, model, idx, Xd, kappa = _search_setup(gv, "d160-C8", fmt, m)
+    Qd = dev(Q)
+    _, t, qhat = gv.project(model, fmt, Qd, want_qc=False)
+    c1, d1 = gv.score_topk(idx, qhat, t, kappa)
+    gv.search_tuning(splits=1, qpw=0, cap=0)
+    try:
+        c2, d2 = gv.score_topk(idx, qhat, t, kappa)
+    finally:
+        gv.search_tuning(0, 0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(c1, c2) and torch.equal(d1, d2)
+    out = G.search(oi, om.A, Q, 10, kappa)
+    tol = reduced_score_tolerance(out, oi, idx.d_pad)
+    n = X.shape[0]
+    c2 = c2.cpu().numpy(); d2 = d2.cpu().numpy()
+    flips = 0
+    for qi in range(m):
+        by_id = np.empty(n); by_id[oi.ids] = out["scores"][qi]
+        tol_id = np.empty(n); tol_id[oi.ids] = tol[qi]
+        flips += check_topk_sets(c2[qi], d2[qi], by_id, tol_id, kappa, f"q{qi}")
+    assert flips <= max(1, m // 50)
+
+
 @pytest.mark.parametrize("fmt", ["fp16", "fp8"])
 @pytest.mark.parametrize("m", [20, 65])
 def test_compaction_path(gv, fmt, m):
