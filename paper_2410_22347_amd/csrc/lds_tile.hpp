@@ -1,7 +1,10 @@
 // Reads of a whole tile from the workgroup's LDS ring, one asm block per
 // shape: every k-step block is requested, then one wait for all of them (the
 // wait sits in the same block, so no load is in flight when the registers are
-// handed back).  lane_addr: LDS byte address of this lane's first element.
+// handed back).  The outputs are early-clobber: a destination must never share
+// a register with the address, which the later reads of the block still use
+// while the earlier ones land.  lane_addr: LDS byte address of this lane's
+// first element.
 #pragma once
 
 #include "search_common.hpp"
@@ -20,7 +23,7 @@ struct LdsTile<2, 16> {
         "ds_read_b128 %0, %2 offset:0\n"
         "ds_read_b128 %1, %2 offset:1024\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1])
+        : "=&v"(d[0]), "=&v"(d[1])
         : "v"(lane_addr)
         : "memory");
   }
@@ -36,7 +39,7 @@ struct LdsTile<4, 16> {
         "ds_read_b128 %2, %4 offset:2048\n"
         "ds_read_b128 %3, %4 offset:3072\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3])
         : "v"(lane_addr)
         : "memory");
   }
@@ -56,7 +59,7 @@ struct LdsTile<8, 16> {
         "ds_read_b128 %6, %8 offset:6144\n"
         "ds_read_b128 %7, %8 offset:7168\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3]), "=v"(d[4]), "=v"(d[5]), "=v"(d[6]), "=v"(d[7])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3]), "=&v"(d[4]), "=&v"(d[5]), "=&v"(d[6]), "=&v"(d[7])
         : "v"(lane_addr)
         : "memory");
   }
@@ -78,7 +81,7 @@ struct LdsTile<10, 16> {
         "ds_read_b128 %8, %10 offset:8192\n"
         "ds_read_b128 %9, %10 offset:9216\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3]), "=v"(d[4]), "=v"(d[5]), "=v"(d[6]), "=v"(d[7]), "=v"(d[8]), "=v"(d[9])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3]), "=&v"(d[4]), "=&v"(d[5]), "=&v"(d[6]), "=&v"(d[7]), "=&v"(d[8]), "=&v"(d[9])
         : "v"(lane_addr)
         : "memory");
   }
@@ -102,7 +105,7 @@ struct LdsTile<12, 16> {
         "ds_read_b128 %10, %12 offset:10240\n"
         "ds_read_b128 %11, %12 offset:11264\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3]), "=v"(d[4]), "=v"(d[5]), "=v"(d[6]), "=v"(d[7]), "=v"(d[8]), "=v"(d[9]), "=v"(d[10]), "=v"(d[11])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3]), "=&v"(d[4]), "=&v"(d[5]), "=&v"(d[6]), "=&v"(d[7]), "=&v"(d[8]), "=&v"(d[9]), "=&v"(d[10]), "=&v"(d[11])
         : "v"(lane_addr)
         : "memory");
   }
@@ -130,7 +133,7 @@ struct LdsTile<16, 16> {
         "ds_read_b128 %14, %16 offset:14336\n"
         "ds_read_b128 %15, %16 offset:15360\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3]), "=v"(d[4]), "=v"(d[5]), "=v"(d[6]), "=v"(d[7]), "=v"(d[8]), "=v"(d[9]), "=v"(d[10]), "=v"(d[11]), "=v"(d[12]), "=v"(d[13]), "=v"(d[14]), "=v"(d[15])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3]), "=&v"(d[4]), "=&v"(d[5]), "=&v"(d[6]), "=&v"(d[7]), "=&v"(d[8]), "=&v"(d[9]), "=&v"(d[10]), "=&v"(d[11]), "=&v"(d[12]), "=&v"(d[13]), "=&v"(d[14]), "=&v"(d[15])
         : "v"(lane_addr)
         : "memory");
   }
@@ -144,7 +147,7 @@ struct LdsTile<2, 8> {
         "ds_read_b64 %0, %2 offset:0\n"
         "ds_read_b64 %1, %2 offset:512\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1])
+        : "=&v"(d[0]), "=&v"(d[1])
         : "v"(lane_addr)
         : "memory");
   }
@@ -160,7 +163,7 @@ struct LdsTile<4, 8> {
         "ds_read_b64 %2, %4 offset:1024\n"
         "ds_read_b64 %3, %4 offset:1536\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3])
         : "v"(lane_addr)
         : "memory");
   }
@@ -180,7 +183,7 @@ struct LdsTile<8, 8> {
         "ds_read_b64 %6, %8 offset:3072\n"
         "ds_read_b64 %7, %8 offset:3584\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3]), "=v"(d[4]), "=v"(d[5]), "=v"(d[6]), "=v"(d[7])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3]), "=&v"(d[4]), "=&v"(d[5]), "=&v"(d[6]), "=&v"(d[7])
         : "v"(lane_addr)
         : "memory");
   }
@@ -202,7 +205,7 @@ struct LdsTile<10, 8> {
         "ds_read_b64 %8, %10 offset:4096\n"
         "ds_read_b64 %9, %10 offset:4608\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3]), "=v"(d[4]), "=v"(d[5]), "=v"(d[6]), "=v"(d[7]), "=v"(d[8]), "=v"(d[9])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3]), "=&v"(d[4]), "=&v"(d[5]), "=&v"(d[6]), "=&v"(d[7]), "=&v"(d[8]), "=&v"(d[9])
         : "v"(lane_addr)
         : "memory");
   }
@@ -226,7 +229,7 @@ struct LdsTile<12, 8> {
         "ds_read_b64 %10, %12 offset:5120\n"
         "ds_read_b64 %11, %12 offset:5632\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3]), "=v"(d[4]), "=v"(d[5]), "=v"(d[6]), "=v"(d[7]), "=v"(d[8]), "=v"(d[9]), "=v"(d[10]), "=v"(d[11])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3]), "=&v"(d[4]), "=&v"(d[5]), "=&v"(d[6]), "=&v"(d[7]), "=&v"(d[8]), "=&v"(d[9]), "=&v"(d[10]), "=&v"(d[11])
         : "v"(lane_addr)
         : "memory");
   }
@@ -254,44 +257,11 @@ struct LdsTile<16, 8> {
         "ds_read_b64 %14, %16 offset:7168\n"
         "ds_read_b64 %15, %16 offset:7680\n"
         "s_waitcnt lgkmcnt(0)"
-        : "=v"(d[0]), "=v"(d[1]), "=v"(d[2]), "=v"(d[3]), "=v"(d[4]), "=v"(d[5]), "=v"(d[6]), "=v"(d[7]), "=v"(d[8]), "=v"(d[9]), "=v"(d[10]), "=v"(d[11]), "=v"(d[12]), "=v"(d[13]), "=v"(d[14]), "=v"(d[15])
+        : "=&v"(d[0]), "=&v"(d[1]), "=&v"(d[2]), "=&v"(d[3]), "=&v"(d[4]), "=&v"(d[5]), "=&v"(d[6]), "=&v"(d[7]), "=&v"(d[8]), "=&v"(d[9]), "=&v"(d[10]), "=&v"(d[11]), "=&v"(d[12]), "=&v"(d[13]), "=&v"(d[14]), "=&v"(d[15])
         : "v"(lane_addr)
         : "memory");
   }
 };
-
-// One lane's 16 accumulator values into LDS, and one of them back by a
-// per-lane index.  Written as asm so that these LDS accesses are not ordered
-// after the tile copies still landing in the ring (the compiler cannot tell
-// the two regions apart and would otherwise wait for every copy in flight).
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void lds_put16(uint32_t addr, const f32x16& v) {
-  const f32x4_t v0 = __builtin_shufflevector(v, v, 0, 1, 2, 3);
-  const f32x4_t v1 = __builtin_shufflevector(v, v, 4, 5, 6, 7);
-  const f32x4_t v2 = __builtin_shufflevector(v, v, 8, 9, 10, 11);
-  const f32x4_t v3 = __builtin_shufflevector(v, v, 12, 13, 14, 15);
-  asm volatile(
-      "ds_write_b128 %0, %1 offset:0\n"
-      "ds_write_b128 %0, %2 offset:16\n"
-      "ds_write_b128 %0, %3 offset:32\n"
-      "ds_write_b128 %0, %4 offset:48\n"
-      "s_waitcnt lgkmcnt(0)"
-      :
-      : "v"(addr), "v"(v0), "v"(v1), "v"(v2), "v"(v3)
-      : "memory");
-}
-
-__device__ __forceinline__ float lds_get(uint32_t addr) {
-  float r;
-  asm volatile(
-      "ds_read_b32 %0, %1\n"
-      "s_waitcnt lgkmcnt(0)"
-      : "=v"(r)
-      : "v"(addr)
-      : "memory");
-  return r;
-}
 
 }  // namespace scan
 }  // namespace gv

@@ -123,35 +123,68 @@ struct WaveSmem {
   uint32_t kept;
   uint64_t idk[CAPL];  // compaction: keys ordered by (score desc, id asc)
   uint32_t row[CAPL];  //             and the stored row of each
-  f32x16 acc[64];      // survivor extraction: one lane's 16 scores, indexed per lane
 };
 
-// Reduce the list L of n keys (n > keep) to its `keep` best by (score desc,
-// original id asc); the kept keys are rewritten to L[0..keep).  Returns the
-// score of the keep-th best.
+// Reduce the list L of n keys (n > keep), keyed (score desc, stored row asc),
+// so that it still holds the `keep` best by (score desc, original id asc).
+// Usual case: every key whose score reaches the keep-th best score stays (ties
+// at that score included, whatever their ids), no id is looked up, and the new
+// length is returned if it is at most `room`.  Otherwise the keys are re-keyed
+// by original id and exactly `keep` stay.  *tk: the keep-th best score.
 template <typename W>
-__device__ float compact_list(uint64_t* L, int n, int keep, const int32_t* __restrict__ ids, W& w) {
+__device__ int compact_list(uint64_t* L, int n, int keep, int room, const int32_t* __restrict__ ids, W& w,
+                            float* tk) {
   const int lane = threadIdx.x & 63;
   // the keys were stored by lanes of this wavefront: make them visible and
-  // read them coherently from L2
+  // read them coherently from L2, four loads in flight per lane
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-  for (int i = lane; i < n; i += 64) {
-    const uint64_t k = __hip_atomic_load(L + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t row = 0xFFFFFFFFu - (uint32_t)k;
-    const uint32_t id = (uint32_t)ids[row];
-    w.idk[i] = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - id);
-    w.row[i] = row;
+  for (int i0 = 0; i0 < n; i0 += 256) {
+    uint64_t k[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 64 + lane;
+      k[u] = i < n ? __hip_atomic_load(L + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 64 + lane;
+      if (i < n) w.idk[i] = k[u];
+    }
   }
   wave_sync();
   const uint64_t kth = wave_kth([&](int i) { return w.idk[i]; }, n, keep, w.hist);
+  *tk = key_score(kth);
+  const uint64_t lo = kth & 0xFFFFFFFF00000000ull;  // smallest key with the keep-th best score
+  int c = 0;
+  for (int i = lane; i < n; i += 64) c += w.idk[i] >= lo;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if (c <= room) {
+    if (lane == 0) w.kept = 0;
+    wave_sync();
+    for (int i = lane; i < n; i += 64) {
+      const uint64_t k = w.idk[i];
+      if (k >= lo) L[atomicAdd(&w.kept, 1u)] = k;
+    }
+    wave_sync();
+    return c;
+  }
+  // many ties at the keep-th best score: exact reduction by original id
+  for (int i = lane; i < n; i += 64) {
+    const uint64_t k = w.idk[i];
+    const uint32_t row = 0xFFFFFFFFu - (uint32_t)k;
+    w.idk[i] = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - (uint32_t)ids[row]);
+    w.row[i] = row;
+  }
+  wave_sync();
+  const uint64_t kid = wave_kth([&](int i) { return w.idk[i]; }, n, keep, w.hist);
   if (lane == 0) w.kept = 0;
   wave_sync();
   for (int i = lane; i < n; i += 64) {
     const uint64_t k = w.idk[i];
-    if (k >= kth) L[atomicAdd(&w.kept, 1u)] = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - w.row[i]);
+    if (k >= kid) L[atomicAdd(&w.kept, 1u)] = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - w.row[i]);
   }
   wave_sync();
-  return key_score(kth);
+  return keep;
 }
 
 // cluster of stored row `row`: the number of j in [1, C) with offsets[j] <= row
@@ -288,6 +321,8 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   // U + 1 tiles; a compaction stages the whole list in this wavefront's LDS,
   // which holds CAPL keys (fewer than the list capacity with an LDS tile ring)
   const int lim = (a.cap < CAPL ? a.cap : CAPL) - kRows * (U + 1);
+  // a compaction that keeps ties may leave at most this many keys (else it is exact)
+  const int room = (lim + a.kappa) / 2;
 
   int cnt[NB];
   int64_t lbase[NB];  // first key slot of this lane's (query, range) list
@@ -308,62 +343,78 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   float tau_s[NB];   // thresholds in the accumulator domain
 
   // --------------------------------------------------------------- epilogue
-  auto epilogue = [&](f32x16 (&A)[NB], int64_t vt, int64_t real_end) __attribute__((always_inline)) {
+  // Padding rows of a segment's last tile never survive (NaN fails every compare).
+  auto mask_padding = [&](f32x16 (&A)[NB], int64_t base, int64_t real_end) __attribute__((always_inline)) {
+    Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+      constexpr int nb = decltype(nbc)::value;
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (base + acc_row(i, half) >= real_end) A[nb][i] = __builtin_nanf("");
+    });
+  };
+
+  // Threshold filter of one scored tile.  mx[nb]: the largest of this lane's 16
+  // scores of query block nb, padding rows included (they are masked here, on
+  // the rare path).  Survivors are appended to the lane's list as keys; the two
+  // lanes holding one query agree on their slots through one lane swap.
+  auto filter = [&](f32x16 (&A)[NB], int64_t vt, int64_t real_end, const float (&mx)[NB], bool valid)
+      __attribute__((always_inline)) {
+    bool any = false;
+    Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+      constexpr int nb = decltype(nbc)::value;
+      any |= mx[nb] >= tau_s[nb];
+    });
+    any = any && valid;  // the maxima are taken unconditionally, beside the matrix core
+    if (__ballot(any) == 0) return;
     const int64_t base = vt * stride * kRows;  // first stored row of the tile
-    if (base + kRows > real_end) {              // last tile of a segment: mask its padding rows
-      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
-        constexpr int nb = decltype(nbc)::value;
+    if (base + kRows > real_end) mask_padding(A, base, real_end);
+    Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+      constexpr int nb = decltype(nbc)::value;
+      const float t = tau_s[nb];
+      if (__ballot(mx[nb] >= t) == 0) return;
+      uint32_t mask = 0;  // survivors among this lane's 16 scores
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-          if (base + acc_row(i, half) >= real_end) A[nb][i] = __builtin_nanf("");
-      });
-    }
-    if constexpr (MODE == kDense) {
-      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
-        constexpr int nb = decltype(nbc)::value;
-        const int64_t q = q0 + nb * 32 + col;
-        if (q < a.m) {
-          float* drow = a.dense + q * ns + vt * kRows;
+      for (int i = 0; i < 16; ++i) mask |= A[nb][i] >= t ? (1u << i) : 0u;
+      const int p = __builtin_popcount(mask);
+      const int pp = other_half(p);  // the other lane holding this query
+      int64_t o = lbase[nb] + cnt[nb] + (half ? pp : 0);  // list slot of this lane's first survivor
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const float v = A[nb][i];
-            drow[acc_row(i, half)] = (v == v) ? v * st[nb] : -INFINITY;
-          }
+      for (int i = 0; i < 16; ++i) {
+        if (mask & (1u << i)) {
+          a.buf[o] = make_key(A[nb][i] * st[nb], (uint32_t)(base + acc_row(i, half)));
+          ++o;
         }
-      });
+      }
+      cnt[nb] += p + pp;
+    });
+  };
+
+  // every score of one tile, for the dense sample
+  auto dense_out = [&](f32x16 (&A)[NB], int64_t vt, int64_t real_end) __attribute__((always_inline)) {
+    const int64_t base = vt * stride * kRows;
+    if (base + kRows > real_end) mask_padding(A, base, real_end);
+    Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+      constexpr int nb = decltype(nbc)::value;
+      const int64_t q = q0 + nb * 32 + col;
+      if (q < a.m) {
+        float* drow = a.dense + q * ns + vt * kRows;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const float v = A[nb][i];
+          drow[acc_row(i, half)] = (v == v) ? v * st[nb] : -INFINITY;
+        }
+      }
+    });
+  };
+
+  // filter (or dense output) of a tile whose maxima are not yet known
+  auto epilogue = [&](f32x16 (&A)[NB], int64_t vt, int64_t real_end) __attribute__((always_inline)) {
+    if constexpr (MODE == kDense) {
+      dense_out(A, vt, real_end);
     } else {
       float mx[NB];
-      bool any = false;
-      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
-        constexpr int nb = decltype(nbc)::value;
-        mx[nb] = max16(A[nb]);
-        any |= mx[nb] >= tau_s[nb];
-      });
-      if (__ballot(any)) {
-        Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
-          constexpr int nb = decltype(nbc)::value;
-          if (__ballot(mx[nb] >= tau_s[nb]) == 0) return;
-          const float t = tau_s[nb];
-          uint32_t mask = 0;  // survivors among this lane's 16 scores
-#pragma unroll
-          for (int i = 0; i < 16; ++i) mask |= A[nb][i] >= t ? (1u << i) : 0u;
-          const int p = __builtin_popcount(mask);
-          const int pp = other_half(p);  // the other lane holding this query
-          int64_t o = lbase[nb] + cnt[nb] + (half ? pp : 0);  // list slot of this lane's first survivor
-          // scores by per-lane index go through LDS
-          const uint32_t my = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) f32x16*)&w.acc[lane]);
-          lds_put16(my, A[nb]);
-          while (__ballot(mask != 0)) {  // as many rounds as the busiest lane has survivors
-            if (mask) {
-              const int i = __builtin_ctz(mask);
-              mask &= mask - 1;
-              a.buf[o] = make_key(lds_get(my + 4 * i) * st[nb], (uint32_t)(base + (i & 3) + 8 * (i >> 2) + 4 * half));
-              ++o;
-            }
-          }
-          cnt[nb] += p + pp;
-        });
-      }
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) { mx[decltype(nbc)::value] = max16(A[decltype(nbc)::value]); });
+      filter(A, vt, real_end, mx, true);
     }
   };
 
@@ -381,12 +432,13 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           fm &= fm - 1;
           const int n = __shfl(cnt[nb], cc);
           const int64_t lb = __shfl(lbase[nb], cc);
-          const float tk = compact_list(a.buf + lb, n, a.kappa, a.ids, w);
+          float tk;
+          const int kept = compact_list(a.buf + lb, n, a.kappa, room, a.ids, w, &tk);
           const int lq = nb * 32 + cc;
           if (lane == 0) w.tau[lq] = fmaxf(w.tau[lq], tk);
           wave_sync();
           if (col == cc) {
-            cnt[nb] = a.kappa;
+            cnt[nb] = kept;
             tau_s[nb] = w.tau[lq] * inv_st[nb];
           }
         }
@@ -426,6 +478,37 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
       const uint8_t* p = xl + (vv < v1 ? vv : v1 - 1) * stride * tile_bytes;
 #pragma unroll
       for (int s = 0; s < KS; ++s) dst[s] = *(const S*)(p + s * kblock);
+    };
+    // matrix-core chain of one tile with the maxima of the previous tile's
+    // scores (Pv) computed between its steps: the vector ALU work runs while
+    // the matrix core is busy instead of after it
+    auto mma_tile_max = [&](const S (&src)[KS], f32x16 (&A)[NB], const f32x16 (&Pv)[NB], float (&mx)[NB])
+        __attribute__((always_inline)) {
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+        constexpr int nb = decltype(nbc)::value;
+        A[nb] = f32x16{0};
+        mx[nb] = Pv[nb][0];
+      });
+      Unroll<0, KS>::run([&](auto sc) __attribute__((always_inline)) {
+        constexpr int st_ = decltype(sc)::value;
+        const T av = Op::cvt(src[st_]);
+        Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+          constexpr int nb = decltype(nbc)::value;
+          A[nb] = Op::mma(av, bq[nb][st_], A[nb]);
+        });
+        constexpr int j0 = 1 + st_ * 15 / KS, j1 = 1 + (st_ + 1) * 15 / KS;
+        Unroll<j0, j1>::run([&](auto jc) __attribute__((always_inline)) {
+          constexpr int j = decltype(jc)::value;
+          Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+            constexpr int nb = decltype(nbc)::value;
+            mx[nb] = fmaxf(mx[nb], Pv[nb][j]);
+          });
+        });
+      });
+      Unroll<0, KS * NB>::run([&](auto) __attribute__((always_inline)) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core op
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then up to two vector ALU ops
+      });
     };
     auto mma_tile = [&](const S (&src)[KS], f32x16 (&A)[NB]) __attribute__((always_inline)) {
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) { A[decltype(nbc)::value] = f32x16{0}; });
@@ -484,9 +567,15 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           LdsTile<KS, Op::EPL * Op::EB>::read(cur, ring_lds + slot_rd * TB);
           slot_rd = slot_rd + 1 == PL ? 0 : slot_rd + 1;
           issue(vt + PL - 1);
-          if constexpr (u & 1) mma_tile(cur, acc1); else mma_tile(cur, acc0);
-          if (vt > v0) {
-            if constexpr (u & 1) epilogue(acc0, vt - 1, real_end); else epilogue(acc1, vt - 1, real_end);
+          if constexpr (MODE == kFilter) {
+            float mx[NB];
+            if constexpr (u & 1) mma_tile_max(cur, acc1, acc0, mx); else mma_tile_max(cur, acc0, acc1, mx);
+            if constexpr (u & 1) filter(acc0, vt - 1, real_end, mx, vt > v0); else filter(acc1, vt - 1, real_end, mx, vt > v0);
+          } else {
+            if constexpr (u & 1) mma_tile(cur, acc1); else mma_tile(cur, acc0);
+            if (vt > v0) {
+              if constexpr (u & 1) epilogue(acc0, vt - 1, real_end); else epilogue(acc1, vt - 1, real_end);
+            }
           }
         });
         check_overflow();
@@ -508,8 +597,13 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           constexpr int u = decltype(uc)::value;
           const int64_t vt = vb + u;
           load_tile(ring[(u + P - 1) % P], vt + P - 1);
-          if constexpr (DEFER) {
-            // matrix core on tile vt, filter of tile vt - 1
+          if constexpr (DEFER && MODE == kFilter) {
+            // matrix core on tile vt, beside it the maxima of tile vt - 1, then its filter
+            float mx[NB];
+            if constexpr (u & 1) mma_tile_max(ring[u % P], acc1, acc0, mx); else mma_tile_max(ring[u % P], acc0, acc1, mx);
+            const bool valid = (u > 0 || vt > v0) && vt - 1 < v1;
+            if constexpr (u & 1) filter(acc0, vt - 1, real_end, mx, valid); else filter(acc1, vt - 1, real_end, mx, valid);
+          } else if constexpr (DEFER) {
             if constexpr (u & 1) mma_tile(ring[u % P], acc1); else mma_tile(ring[u % P], acc0);
             if ((u > 0 || vt > v0) && vt - 1 < v1) {
               if constexpr (u & 1) epilogue(acc0, vt - 1, real_end); else epilogue(acc1, vt - 1, real_end);
