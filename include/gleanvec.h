@@ -147,9 +147,13 @@ void gv_model_destroy(gv_model* model);
  *
  * X       device, n x D FP32 database vectors (n >= 1).
  * fmt     storage format of the reduced vectors.
- * copy_X  nonzero: the index keeps its own copy of X (for the full-dimension
- *         rerank); zero: it borrows X, which must then outlive the index and
- *         stay unchanged.
+ * copy_X  1: the index keeps its own copy of X (for the full-dimension
+ *         rerank); 0: it borrows X, which must then outlive the index and stay
+ *         unchanged; 2: it keeps no full-dimension vectors (searches then
+ *         rerank from the stored vectors, gv_search_flex with
+ *         GV_RERANK_STORED).
+ * The reduced dimension d of the model may be anything up to D (d > 256 is
+ * stored, and searched through a leading part with gv_search_flex).
  *
  * Computes tag_i = arg-max_c <x_i, mu_c> in FP64 (lowest c on ties), groups the
  * rows by tag (stable: increasing ids inside a cluster), computes
@@ -253,7 +257,7 @@ gv_status gv_score_topk(const gv_index* index, const void* qhat, const float* t,
                         int32_t kappa, int32_t* cand_ids, float* cand_scores, void* stream);
 
 /*
- * gv_rerank -- stage S4 (Algorithm 1, postprocessing).
+ * gv_rerank -- stage S4 (Algorithm 1, postprocessing); the index must keep X.
  * Q device m x D FP32; cand_ids device m x kappa int32 (valid original ids);
  * out_ids device m x k int32, out_scores device m x k FP32 (may be NULL):
  * the k best exact <q, x> (FP64 accumulation) among the candidates, ordered by
@@ -261,6 +265,70 @@ gv_status gv_score_topk(const gv_index* index, const void* qhat, const float* t,
  */
 gv_status gv_rerank(const gv_index* index, const float* Q, int64_t m, const int32_t* cand_ids,
                     int32_t kappa, int32_t k, int32_t* out_ids, float* out_scores, void* stream);
+
+/* ------------------------------------------------------------------ flexible d */
+
+/* Rerank source of gv_search_flex. */
+enum {
+  GV_RERANK_FULL = 0,   /* exact <q, x> from the full-dimension X the index keeps */
+  GV_RERANK_STORED = 1  /* <A_c q, s_c x^> over every stored coordinate */
+};
+
+/*
+ * gv_search_flex -- Algorithm 1 with the reduced dimension chosen at search
+ * time (Section 3.3).  The rows of each P_c are ordered by decreasing
+ * eigenvalue, so the leading d_search coordinates of the stored vectors are
+ * the d_search-dimensional reduction; an index encoded from a model fitted at
+ * a larger d (up to D) serves every d_search <= d without re-encoding.
+ *
+ * d_search    1 <= d_search <= d, gv_padded_dim(d_search) <= 256.
+ * rerank      GV_RERANK_FULL: exact <q, x> from the full-dimension X (the
+ *             index must keep it); GV_RERANK_STORED: <A_c q, x'> with
+ *             x' = s_c x^ the stored vector over all of its d coordinates and
+ *             q_c = fl32(A_c q), FP64 accumulation -- with d = D this is
+ *             <q, x> up to the storage rounding, and no second copy of the
+ *             database is needed.
+ * Other arguments and outputs as gv_search.  S1 computes q_c over all d rows;
+ * the scale t and the view q^ come from its first d_search values; S2 reads
+ * the leading gv_padded_dim(d_search) coordinates of every stored row.
+ *
+ * Errors: as gv_search; GV_EINVAL also for an out-of-range d_search, or for
+ * GV_RERANK_FULL on an index that keeps no X.
+ */
+gv_status gv_search_flex(const gv_model* model, const gv_index* index, const float* Q, int64_t m,
+                         int32_t k, int32_t kappa, int32_t d_search, int32_t rerank,
+                         int32_t* out_ids, float* out_scores, void* stream);
+
+/*
+ * gv_project_flex -- stage S1 of gv_search_flex.  qc device m x C x d_pad FP32
+ * (d_pad = gv_padded_dim(d); may be NULL): q_c over all d rows, zero padded.
+ * t device m x C FP32: scales of the first d_search values.  qhat device
+ * m x C x gv_padded_dim(d_search) elements of `fmt`: the views of the first
+ * d_search values, zero padded.  Errors as gv_search_flex.
+ */
+gv_status gv_project_flex(const gv_model* model, gv_format fmt, const float* Q, int64_t m,
+                          int32_t d_search, float* qc, float* t, void* qhat, void* stream);
+
+/*
+ * gv_score_topk_flex -- stages S2 and S3 on the leading d_search coordinates,
+ * for views written by gv_project_flex with the same d_search.  Outputs as
+ * gv_score_topk.  Errors as gv_search_flex.
+ */
+gv_status gv_score_topk_flex(const gv_index* index, const void* qhat, const float* t, int64_t m,
+                             int32_t d_search, int32_t kappa, int32_t* cand_ids, float* cand_scores,
+                             void* stream);
+
+/*
+ * gv_rerank_stored -- stage S4 from the stored vectors (Section 3.3).
+ * qc device m x C x d_pad FP32 as written by gv_project_flex (or gv_project);
+ * cand_ids device m x kappa int32 (original ids; negative entries are
+ * skipped).  out_ids device m x k int32, out_scores device m x k FP32 (may
+ * be NULL): the k best <q_c, s_c x^_i> (c the candidate's cluster, FP64
+ * accumulation over all d_pad coordinates), ordered by (score desc, id asc).
+ * Errors as gv_search.
+ */
+gv_status gv_rerank_stored(const gv_index* index, const float* qc, int64_t m, const int32_t* cand_ids,
+                           int32_t kappa, int32_t k, int32_t* out_ids, float* out_scores, void* stream);
 
 /*
  * gv_search_tuning -- override the launch shape of S2/S3 for the calling

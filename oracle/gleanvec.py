@@ -335,6 +335,82 @@ def search(index: Index, A: np.ndarray, Q: np.ndarray, k: int, kappa: int):
                 ids=out_ids, out_scores=out_sc)
 
 
+# ============================================================================ flexible d
+# Section 3.3: the stored vectors keep d_s >= d coordinates ordered by decreasing
+# eigenvalue of W K_X W (the rows of P come sorted that way), so a search may use
+# any leading d of them, fixed at search time; and the stored vectors themselves
+# can serve the rerank, <q, x> ~ <A q, x'> with x' the stored coordinates (exact
+# when d_s = D and K_Q has full rank, since then A^T B = I).
+
+def project_queries_flex(A: np.ndarray, Q: np.ndarray, fmt: str, d_search: int):
+    """Eager views on the leading d_search coordinates: q_c = fl32(A_c q) over all
+    d_s stored rows (the rerank from stored vectors uses them all); the scale t and
+    the storage-format view q^ come from the first d_search values only.
+    Returns (q_c [m, C, d_s], t [m, C], q^ [m, C, d_search])."""
+    A64 = np.asarray(A, np.float64)
+    Q64 = np.asarray(Q, np.float64)
+    C, d, D = A64.shape
+    assert 1 <= d_search <= d
+    qc = formats.round_to("fp32", (Q64 @ A64.reshape(C * d, D).T).reshape(-1, C, d))
+    lead = qc[:, :, :d_search]
+    t = formats.pow2_scale(fmt, np.max(np.abs(lead), axis=2))
+    qh = formats.round_to(fmt, lead / t[:, :, None])
+    return qc, t, qh
+
+
+def reduced_scores_flex(index: Index, t: np.ndarray, qh: np.ndarray, d_search: int) -> np.ndarray:
+    """Eq. 11 on the leading d_search stored coordinates: for x_i in cluster c,
+    s_i = s_c * t_{q,c} * sum_{j < d_search} q^_{c,j} x^_{i,j}, float64, grouped order."""
+    m = qh.shape[0]
+    n = index.xq.shape[0]
+    out = np.empty((m, n))
+    for c in range(index.offsets.shape[0] - 1):
+        a, b = index.offsets[c], index.offsets[c + 1]
+        if a == b:
+            continue
+        out[:, a:b] = (qh[:, c, :d_search] @ index.xq[a:b, :d_search].T) * (index.scale[c] * t[:, c])[:, None]
+    return out
+
+
+def rerank_stored(index: Index, qc: np.ndarray, q: int, cand_ids: np.ndarray):
+    """Rerank of one query's candidates from the stored vectors (Section 3.3):
+    <A_c q, x'_i> = sum_j q_{c,j} * (s_c x^_{i,j}) over every stored coordinate,
+    float64, c the candidate's cluster.  Returns the scores of cand_ids."""
+    pos_of = np.empty(index.ids.shape[0], np.int64)
+    pos_of[index.ids] = np.arange(index.ids.shape[0])
+    out = np.empty(cand_ids.shape[0])
+    for r, i in enumerate(cand_ids):
+        c = index.tags[i]
+        out[r] = float(np.dot(qc[q, c], index.xq[pos_of[i]] * index.scale[c]))
+    return out
+
+
+def search_flex(index: Index, A: np.ndarray, Q: np.ndarray, k: int, kappa: int, d_search: int,
+                rerank: str = "full"):
+    """Algorithm 1 with the reduced dimension chosen at search time (Section 3.3):
+    the main step scores the leading d_search coordinates; the rerank uses the full
+    vectors (rerank = "full") or the stored ones (rerank = "stored")."""
+    qc, t, qh = project_queries_flex(A, Q, index.fmt, d_search)
+    S = reduced_scores_flex(index, t, qh, d_search)
+    m = Q.shape[0]
+    cand_ids = np.empty((m, kappa), np.int64)
+    cand_sc = np.empty((m, kappa))
+    out_ids = np.empty((m, k), np.int64)
+    out_sc = np.empty((m, k))
+    Q64 = np.asarray(Q, np.float64)
+    for qi in range(m):
+        ci, cs = topk(S[qi], index.ids, kappa)
+        cand_ids[qi], cand_sc[qi] = ci, cs
+        if rerank == "stored":
+            exact = rerank_stored(index, qc, qi, ci)
+        else:
+            exact = np.asarray(index.X[ci], np.float64) @ Q64[qi]
+        oi, os_ = topk(exact, ci, k)
+        out_ids[qi], out_sc[qi] = oi, os_
+    return dict(qc=qc, t=t, qh=qh, scores=S, cand_ids=cand_ids, cand_scores=cand_sc,
+                ids=out_ids, out_scores=out_sc)
+
+
 def exact_topk(X: np.ndarray, Q: np.ndarray, k: int, chunk: int = 1 << 18):
     """Ground truth: the k largest <q, x_i> over all i (Section 2), float64, streamed
     over row chunks with a running merge."""

@@ -29,6 +29,7 @@ EXPORTED = [
     "gv_index_export", "gv_index_destroy", "gv_search", "gv_project", "gv_score_topk",
     "gv_rerank", "gv_search_tuning", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
     "gv_padded_dim", "gv_tags", "gv_moments", "gv_loss_grad", "gv_search_batched", "gv_batch_release",
+    "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored",
 ]
 
 
@@ -78,6 +79,10 @@ _sig("gv_project", [_vp, ctypes.c_int, _vp, _i64, _vp, _vp, _vp, _vp])
 _sig("gv_score_topk", [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp])
 _sig("gv_rerank", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_search_tuning", [_i32, _i32, _i32])
+_sig("gv_search_flex", [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp])
+_sig("gv_project_flex", [_vp, ctypes.c_int, _vp, _i64, _i32, _vp, _vp, _vp, _vp])
+_sig("gv_score_topk_flex", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
+_sig("gv_rerank_stored", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_padded_dim", [_i32], _i32)
 _sig("gv_host_eigh", [_i32, _vp, _vp, _vp])
 _sig("gv_profile_enable", [_i32])
@@ -202,13 +207,15 @@ def model_import(mu, A, B) -> Model:
     return Model(h)
 
 
-def encode(model: Model, X, fmt, copy_X: bool = False) -> Index:
+def encode(model: Model, X, fmt, copy_X=False) -> Index:
+    """Index build.  copy_X: False borrows X (kept alive by the Index), True copies
+    it, "none" keeps no full-dimension vectors (rerank from the stored ones)."""
     _dev_f32(X)
     f = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+    mode = 2 if copy_X == "none" else (1 if copy_X else 0)
     h = _vp()
-    _check(_lib.gv_encode(model._h, _ptr(X), X.shape[0], f, 1 if copy_X else 0, _stream(), ctypes.byref(h)),
-           "gv_encode")
-    return Index(h, keep=None if copy_X else X)
+    _check(_lib.gv_encode(model._h, _ptr(X), X.shape[0], f, mode, _stream(), ctypes.byref(h)), "gv_encode")
+    return Index(h, keep=X if mode == 0 else None)
 
 
 def search(model: Model, index: Index, Q, k: int, kappa: int, with_scores: bool = True):
@@ -219,6 +226,60 @@ def search(model: Model, index: Index, Q, k: int, kappa: int, with_scores: bool 
     ids = torch.empty((m, k), dtype=torch.int32, device=Q.device)
     sc = torch.empty((m, k), dtype=torch.float32, device=Q.device) if with_scores else None
     _check(_lib.gv_search(model._h, index._h, _ptr(Q), m, k, kappa, _ptr(ids), _ptr(sc), _stream()), "gv_search")
+    return ids, sc
+
+
+RERANK = {"full": 0, "stored": 1}
+
+
+def search_flex(model: Model, index: Index, Q, k: int, kappa: int, d_search: int, rerank: str = "full",
+                with_scores: bool = True):
+    """Search on the leading d_search coordinates (Section 3.3); rerank "full" (exact,
+    from X) or "stored" (from the stored vectors).  Returns (ids, scores or None)."""
+    import torch
+    _dev_f32(Q)
+    m = Q.shape[0]
+    ids = torch.empty((m, k), dtype=torch.int32, device=Q.device)
+    sc = torch.empty((m, k), dtype=torch.float32, device=Q.device) if with_scores else None
+    _check(_lib.gv_search_flex(model._h, index._h, _ptr(Q), m, k, kappa, d_search, RERANK[rerank], _ptr(ids),
+                               _ptr(sc), _stream()), "gv_search_flex")
+    return ids, sc
+
+
+def project_flex(model: Model, fmt, Q, d_search: int):
+    """Stage S1 of search_flex: (q_c [m, C, d_pad] f32 over all d rows, t [m, C],
+    qhat [m, C, padded_dim(d_search)] raw format of the first d_search values)."""
+    import torch
+    _dev_f32(Q)
+    f = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+    m = Q.shape[0]
+    qc = torch.empty((m, model.C, padded_dim(model.d)), dtype=torch.float32, device=Q.device)
+    t = torch.empty((m, model.C), dtype=torch.float32, device=Q.device)
+    qhat = torch.empty((m, model.C, padded_dim(d_search)), dtype=_elem_dtype(f), device=Q.device)
+    _check(_lib.gv_project_flex(model._h, f, _ptr(Q), m, d_search, _ptr(qc), _ptr(t), _ptr(qhat), _stream()),
+           "gv_project_flex")
+    return qc, t, qhat
+
+
+def score_topk_flex(index: Index, qhat, t, d_search: int, kappa: int):
+    """Stages S2 + S3 on the leading d_search coordinates: (cand_ids, cand_scores)."""
+    import torch
+    m = t.shape[0]
+    ids = torch.empty((m, kappa), dtype=torch.int32, device=t.device)
+    sc = torch.empty((m, kappa), dtype=torch.float32, device=t.device)
+    _check(_lib.gv_score_topk_flex(index._h, _ptr(qhat), _ptr(t), m, d_search, kappa, _ptr(ids), _ptr(sc),
+                                   _stream()), "gv_score_topk_flex")
+    return ids, sc
+
+
+def rerank_stored(index: Index, qc, cand_ids, k: int):
+    """Stage S4 from the stored vectors: (ids [m, k] int32, scores [m, k] f32)."""
+    import torch
+    m, kappa = cand_ids.shape
+    ids = torch.empty((m, k), dtype=torch.int32, device=qc.device)
+    sc = torch.empty((m, k), dtype=torch.float32, device=qc.device)
+    _check(_lib.gv_rerank_stored(index._h, _ptr(qc), m, _ptr(cand_ids), kappa, k, _ptr(ids), _ptr(sc), _stream()),
+           "gv_rerank_stored")
     return ids, sc
 
 

@@ -258,7 +258,7 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
     GV_REQUIRE(X != nullptr, "gv_encode: X is NULL");
     GV_REQUIRE(n >= 1 && n <= 0x7fffffffLL, "gv_encode: need 1 <= n < 2^31");
     GV_REQUIRE(fmt >= GV_FP32 && fmt <= GV_FP8_E4M3, "gv_encode: unknown format");
-    GV_REQUIRE(model->d <= 256, "gv_encode: reduced dimension above 256 is not supported");
+    GV_REQUIRE(copy_X >= 0 && copy_X <= 2, "gv_encode: copy_X must be 0, 1 or 2");
     hipStream_t st = (hipStream_t)stream;
     bool fin = false;
     GV_TRY(check_finite_f32(X, n * model->D, st, &fin));
@@ -281,10 +281,11 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
     x->offsets = nullptr;
     x->seg_end = nullptr;
     x->ids = nullptr;
+    x->pos = nullptr;
     x->xlow = nullptr;
     x->scale = nullptr;
     x->X = nullptr;
-    x->own_X = copy_X != 0;
+    x->own_X = copy_X == 1;
     auto fail = [&](gv_status s) {
       gv_index_destroy(x);
       return s;
@@ -306,7 +307,7 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
       if (hipMemcpyAsync(copy, X, sizeof(float) * n * x->D, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return fail(GV_EDEVICE);
     } else {
-      x->X = X;
+      x->X = copy_X == 0 ? X : nullptr;  // 2: no full-dimension vectors kept
     }
     gv_status s = encode_impl(model, X, n, fmt, st, x);
     if (s != GV_OK) return fail(s);
@@ -362,6 +363,7 @@ void gv_index_destroy(gv_index* x) {
   if (x->offsets) (void)hipFree(x->offsets);
   if (x->seg_end) (void)hipFree(x->seg_end);
   if (x->ids) (void)hipFree(x->ids);
+  if (x->pos) (void)hipFree(x->pos);
   if (x->xlow) (void)hipFree(x->xlow);
   if (x->scale) (void)hipFree(x->scale);
   if (x->own_X && x->X) (void)hipFree((void*)x->X);
@@ -435,6 +437,7 @@ gv_status gv_rerank(const gv_index* index, const float* Q, int64_t m, const int3
     GV_TRY(check_search_args(index, m, k, kappa));
     if (m == 0) return GV_OK;
     GV_REQUIRE(Q && cand_ids && out_ids, "gv_rerank: NULL argument");
+    GV_REQUIRE(index->X != nullptr, "gv_rerank: the index keeps no full-dimension vectors (use gv_rerank_stored)");
     return rerank_impl(index, Q, m, cand_ids, kappa, k, out_ids, out_scores, (hipStream_t)stream);
   });
 }
@@ -452,6 +455,73 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
     keep_pool(index->device);
     SearchPlan plan;
     GV_TRY(search_plan(model, index, m, kappa, &plan));
+    void* ws = nullptr;
+    GV_HIP(hipMallocAsync(&ws, plan.bytes, st));
+    const gv_status s = search_run(model, index, Q, m, k, kappa, out_ids, out_scores, plan, ws, st);
+    (void)hipFreeAsync(ws, st);
+    return s;
+  });
+}
+
+// ---------------------------------------------------------------------------- flexible d (Section 3.3)
+static gv_status check_d_search(const gv_model* model, int32_t d_search) {
+  GV_REQUIRE(d_search >= 1 && d_search <= model->d, "d_search must lie in [1, d]");
+  GV_REQUIRE(pad_dim(d_search) <= 256, "the scan reads at most 256 leading coordinates (padded)");
+  return GV_OK;
+}
+
+gv_status gv_project_flex(const gv_model* model, gv_format fmt, const float* Q, int64_t m, int32_t d_search, float* qc,
+                          float* t, void* qhat, void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(model)) return GV_ENOTFIT;
+    GV_REQUIRE(m >= 0, "gv_project_flex: m < 0");
+    GV_REQUIRE(fmt >= GV_FP32 && fmt <= GV_FP8_E4M3, "gv_project_flex: unknown format");
+    GV_TRY(check_d_search(model, d_search));
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(Q && t && qhat, "gv_project_flex: NULL argument");
+    return project_impl(model, fmt, Q, m, qc, t, qhat, (hipStream_t)stream, d_search);
+  });
+}
+
+gv_status gv_score_topk_flex(const gv_index* index, const void* qhat, const float* t, int64_t m, int32_t d_search,
+                             int32_t kappa, int32_t* cand_ids, float* cand_scores, void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(index)) return GV_ENOTFIT;
+    GV_TRY(check_search_args(index, m, 1, kappa));
+    GV_REQUIRE(d_search >= 1 && d_search <= index->d, "gv_score_topk_flex: d_search must lie in [1, d]");
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(qhat && t && cand_ids && cand_scores, "gv_score_topk_flex: NULL argument");
+    return score_topk_impl(index, qhat, t, m, kappa, cand_ids, cand_scores, (hipStream_t)stream, d_search);
+  });
+}
+
+gv_status gv_rerank_stored(const gv_index* index, const float* qc, int64_t m, const int32_t* cand_ids, int32_t kappa,
+                           int32_t k, int32_t* out_ids, float* out_scores, void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(index)) return GV_ENOTFIT;
+    GV_TRY(check_search_args(index, m, k, kappa));
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(qc && cand_ids && out_ids, "gv_rerank_stored: NULL argument");
+    return rerank_stored_impl(index, qc, m, cand_ids, kappa, k, out_ids, out_scores, (hipStream_t)stream);
+  });
+}
+
+gv_status gv_search_flex(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int32_t k,
+                         int32_t kappa, int32_t d_search, int32_t rerank, int32_t* out_ids, float* out_scores,
+                         void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(model) || !valid(index)) return GV_ENOTFIT;
+    GV_REQUIRE(model->C == index->C && model->d == index->d && model->D == index->D,
+               "gv_search_flex: model and index shapes differ");
+    GV_TRY(check_search_args(index, m, k, kappa));
+    GV_TRY(check_d_search(model, d_search));
+    GV_REQUIRE(rerank == GV_RERANK_FULL || rerank == GV_RERANK_STORED, "gv_search_flex: unknown rerank source");
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(Q && out_ids, "gv_search_flex: NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    keep_pool(index->device);
+    SearchPlan plan;
+    GV_TRY(search_plan(model, index, m, kappa, &plan, d_search, rerank == GV_RERANK_STORED));
     void* ws = nullptr;
     GV_HIP(hipMallocAsync(&ws, plan.bytes, st));
     const gv_status s = search_run(model, index, Q, m, k, kappa, out_ids, out_scores, plan, ws, st);

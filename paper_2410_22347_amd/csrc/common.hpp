@@ -69,7 +69,7 @@ inline int pad_dim(int d) {
   const int sizes[] = {32, 64, 128, 160, 192, 256};
   for (int s : sizes)
     if (d <= s) return s;
-  return (d + 15) / 16 * 16;  // beyond 256: rejected by encode
+  return (d + 15) / 16 * 16;  // beyond 256: stored, scanned through a leading part of at most 256
 }
 
 // Scale targets: the block's largest magnitude is mapped into (T/2, T].
@@ -139,6 +139,24 @@ __host__ __device__ inline uint8_t to_fp8(double y) {
   return (uint8_t)round_bits<4, 3>(y, 7, 448.0, 0x7Eu);
 }
 
+// Exact values of the stored bit patterns (IEEE binary16, bfloat16, OCP E4M3).
+__host__ __device__ inline double from_fp16(uint16_t h) {
+  const int e = (h >> 10) & 31, f = h & 1023;
+  const double v = e == 0 ? ldexp((double)f, -24) : ldexp((double)(1024 + f), e - 25);
+  return (h & 0x8000u) ? -v : v;
+}
+__host__ __device__ inline double from_bf16(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
+__host__ __device__ inline double from_fp8(uint8_t c) {
+  const int e = (c >> 3) & 15, f = c & 7;
+  const double v = e == 0 ? ldexp((double)f, -9) : ldexp((double)(8 + f), e - 10);
+  return (c & 0x80u) ? -v : v;
+}
+
 // ---------------------------------------------------------------- ordering key
 // 64-bit key ordering candidates by (score desc, id asc): larger key = better.
 __host__ __device__ inline uint32_t order_f32(float s) {
@@ -186,9 +204,10 @@ struct gv_index {
   int64_t* offsets;  // device C+1, padded segment starts (multiples of 32)
   int64_t* seg_end;  // device C, first padding row of each segment (offsets[c] + rows of c)
   int32_t* ids;      // device n_pad, original id of each stored row, -1 for padding
+  int32_t* pos;      // device n, stored row of each original id
   void* xlow;        // device n_pad x dp elements of fmt, matrix-core tiled
   float* scale;      // device C
-  const float* X;    // device n x D (owned if own_X)
+  const float* X;    // device n x D (owned if own_X), NULL when the index keeps none
   bool own_X;
   std::vector<int64_t> h_offsets;  // padded segment starts
   std::vector<int64_t> h_counts;   // rows per cluster
@@ -203,20 +222,27 @@ gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, 
                    uint64_t seed, const gv_fit_opts* opts, hipStream_t st, gv_model* model);
 gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt, hipStream_t st,
                       gv_index* index);
+// d_search (0: all of the model's d) is the number of leading coordinates the
+// views and the scan use (Section 3.3); q_c always holds all d of them.
 gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m, float* qc,
-                       float* t, void* qhat, hipStream_t st);
+                       float* t, void* qhat, hipStream_t st, int d_search = 0);
 gv_status score_topk_impl(const gv_index* index, const void* qhat, const float* t, int64_t m,
-                          int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st);
+                          int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st, int d_search = 0);
 void keep_pool(int device);
 // one search's scratch, carved from a single workspace (byte offsets)
 struct SearchPlan {
   size_t off_t = 0, off_qc = 0, off_qhat = 0, off_cand = 0, off_csc = 0, off_scan = 0, bytes = 0;
+  int d_search = 0;     // leading coordinates scanned
+  bool stored = false;  // rerank from the stored vectors instead of the full-dimension X
 };
-gv_status search_plan(const gv_model* model, const gv_index* index, int64_t m, int kappa, SearchPlan* plan);
+gv_status search_plan(const gv_model* model, const gv_index* index, int64_t m, int kappa, SearchPlan* plan,
+                      int d_search = 0, bool stored = false);
 gv_status search_run(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int k, int kappa,
                      int32_t* out_ids, float* out_scores, const SearchPlan& plan, void* workspace, hipStream_t st);
 gv_status rerank_impl(const gv_index* index, const float* Q, int64_t m, const int32_t* cand,
                       int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
+gv_status rerank_stored_impl(const gv_index* index, const float* qc, int64_t m, const int32_t* cand,
+                             int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
 gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite);
 gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* tags, hipStream_t st);
 gv_status moments_impl(const float* V, int64_t n, int D, const uint8_t* tags, int C, double* K, hipStream_t st);

@@ -57,7 +57,8 @@ __global__ void k_block_hist(const uint8_t* __restrict__ tags, int64_t n, int C,
 
 // stable scatter: rows of block b are placed in increasing id order after base[c][b]
 __global__ void k_block_scatter(const uint8_t* __restrict__ tags, int64_t n, int C, const int64_t* __restrict__ base,
-                                int64_t nblocks, int32_t* __restrict__ ids, int64_t* __restrict__ ids64) {
+                                int64_t nblocks, int32_t* __restrict__ ids, int64_t* __restrict__ ids64,
+                                int32_t* __restrict__ pos) {
   __shared__ uint8_t t[kBlockRows];
   __shared__ int64_t cnt[256];
   const int64_t r0 = (int64_t)blockIdx.x * kBlockRows;
@@ -70,6 +71,7 @@ __global__ void k_block_scatter(const uint8_t* __restrict__ tags, int64_t n, int
       int64_t p = cnt[t[i]]++;
       ids[p] = (int32_t)(r0 + i);
       ids64[p] = r0 + i;
+      pos[r0 + i] = (int32_t)p;
     }
   }
 }
@@ -177,6 +179,7 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
     idx->h_offsets[C] = run;
     idx->n_pad = run;
     GV_HIP(hipMalloc((void**)&idx->ids, sizeof(int32_t) * std::max<int64_t>(run, 1)));
+    GV_HIP(hipMalloc((void**)&idx->pos, sizeof(int32_t) * n));
     GV_HIP(hipMalloc(&idx->xlow, (size_t)std::max<int64_t>(run, 1) * dp * fmt_bytes(fmt)));
     GV_HIP(hipMallocAsync((void**)&ids64, sizeof(int64_t) * std::max<int64_t>(run, 1), st));
     GV_HIP(hipMemsetAsync(idx->ids, 0xFF, sizeof(int32_t) * run, st));  // -1: padding
@@ -186,7 +189,7 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
     for (int c = 0; c < C; ++c) h_end[c] = idx->h_offsets[c] + idx->h_counts[c];
     GV_HIP(hipMemcpyAsync(idx->seg_end, h_end.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nb), dim3(64), 0, st, idx->tags, n, C, base, nb, idx->ids,
-                       ids64);
+                       ids64, idx->pos);
     GV_HIP(hipGetLastError());
     GV_HIP(hipFreeAsync(hist, st));
     GV_HIP(hipFreeAsync(base, st));

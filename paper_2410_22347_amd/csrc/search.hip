@@ -13,28 +13,29 @@ namespace gv {
 // ============================================================================ S1
 namespace {
 
-// One wavefront per (query, cluster): amax of q_c, power-of-two scale t, the
-// storage-format view rnd(q_c / t) (zero padded); also zero-pads q_c.
+// One wavefront per (query, cluster): zero-pads q_c (row pitch dq) past its d
+// values; the power-of-two scale t of its first ds values and the
+// storage-format view rnd(q_c / t) of them (row pitch dpo, zero padded).
 template <int FMT>
-__global__ void k_quant_queries(float* __restrict__ qc, int64_t m, int C, int d, int dp, double T,
+__global__ void k_quant_queries(float* __restrict__ qc, int64_t m, int C, int d, int dq, int ds, int dpo, double T,
                                 float* __restrict__ t_out, void* __restrict__ qhat) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (w >= m * C) return;
-  float* v = qc + w * dp;
+  float* v = qc + w * dq;
+  for (int j = d + lane; j < dq; j += 64) v[j] = 0.0f;
   float amax = 0.0f;
-  for (int j = lane; j < d; j += 64) amax = fmaxf(amax, fabsf(v[j]));
+  for (int j = lane; j < ds; j += 64) amax = fmaxf(amax, fabsf(v[j]));
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
   const float t = (FMT == GV_FP32) ? 1.0f : pow2_scale(amax, T);
   if (lane == 0) t_out[w] = t;
-  for (int j = lane; j < dp; j += 64) {
-    float x = (j < d) ? v[j] : 0.0f;
-    if (j >= d) v[j] = 0.0f;
-    double y = (double)x / (double)t;  // exact: t is a power of two
-    if (FMT == GV_FP32) ((float*)qhat)[w * dp + j] = x;
-    else if (FMT == GV_FP16) ((uint16_t*)qhat)[w * dp + j] = to_fp16(y);
-    else if (FMT == GV_BF16) ((uint16_t*)qhat)[w * dp + j] = to_bf16(y);
-    else ((uint8_t*)qhat)[w * dp + j] = to_fp8(y);
+  for (int j = lane; j < dpo; j += 64) {
+    const float x = (j < ds) ? v[j] : 0.0f;
+    const double y = (double)x / (double)t;  // exact: t is a power of two
+    if (FMT == GV_FP32) ((float*)qhat)[w * dpo + j] = x;
+    else if (FMT == GV_FP16) ((uint16_t*)qhat)[w * dpo + j] = to_fp16(y);
+    else if (FMT == GV_BF16) ((uint16_t*)qhat)[w * dpo + j] = to_bf16(y);
+    else ((uint8_t*)qhat)[w * dpo + j] = to_fp8(y);
   }
 }
 
@@ -62,8 +63,9 @@ __global__ __launch_bounds__(256) void k_project_small(const float* __restrict__
 }  // namespace
 
 gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m, float* qc, float* t, void* qhat,
-                       hipStream_t st) {
+                       hipStream_t st, int d_search) {
   const int C = model->C, d = model->d, D = model->D, dp = pad_dim(d);
+  const int ds = d_search > 0 ? d_search : d, dpo = pad_dim(ds);
   float* tmp = nullptr;
   if (!qc) {
     GV_HIP(hipMallocAsync((void**)&tmp, sizeof(float) * m * C * dp, st));
@@ -85,10 +87,10 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
     const unsigned grid = (unsigned)((m * C + 3) / 4);
     const double T = scale_target(fmt);
     switch (fmt) {
-      case GV_FP32: hipLaunchKernelGGL(k_quant_queries<GV_FP32>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, T, t, qhat); break;
-      case GV_FP16: hipLaunchKernelGGL(k_quant_queries<GV_FP16>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, T, t, qhat); break;
-      case GV_BF16: hipLaunchKernelGGL(k_quant_queries<GV_BF16>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, T, t, qhat); break;
-      default: hipLaunchKernelGGL(k_quant_queries<GV_FP8_E4M3>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, T, t, qhat); break;
+      case GV_FP32: hipLaunchKernelGGL(k_quant_queries<GV_FP32>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
+      case GV_FP16: hipLaunchKernelGGL(k_quant_queries<GV_FP16>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
+      case GV_BF16: hipLaunchKernelGGL(k_quant_queries<GV_BF16>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
+      default: hipLaunchKernelGGL(k_quant_queries<GV_FP8_E4M3>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
     }
   }
   if (tmp) GV_HIP(hipFreeAsync(tmp, st));
@@ -340,12 +342,18 @@ struct ScanPlan {
   int Rmax = 1;
   int64_t ns = 0;
   int cap = kCap;
+  int dp = 0;  // padded length of the scanned leading part of each row
   size_t off_buf = 0, off_cnt = 0, off_seed = 0, off_dense = 0, bytes = 0;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p) {
+gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int d_search = 0) {
+  p->dp = pad_dim(d_search > 0 ? d_search : idx->d);
+  if (p->dp > idx->dp || p->dp > 256) {
+    set_error("the scan reads at most the leading 256 stored coordinates (padded), and no more than the index stores");
+    return GV_EUNSUPPORTED;
+  }
   p->cap = tuned_cap() > 0 ? tuned_cap() : kCap;
   if (p->cap < min_list_cap(kappa) || p->cap > kCap) {
     set_error("candidate list capacity must lie in [kappa + 417, 2048]");
@@ -358,7 +366,7 @@ gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p) {
   p->Rmax = 1;
   for (size_t li = 0; li < p->levels.size(); ++li) {
     const int64_t s = p->levels[li];
-    const Shape sh = choose_shape(idx->fmt, idx->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
+    const Shape sh = choose_shape(idx->fmt, p->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
     if (!(p->has_dense && li == 0)) p->Rmax = std::max(p->Rmax, sh.R);  // the dense scan writes no lists
     p->shapes.push_back(sh);
   }
@@ -399,7 +407,8 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
   args.m = m;
   args.n_pad = idx->n_pad;
   args.C = idx->C;
-  args.dp = idx->dp;
+  args.dp = p.dp;
+  args.dps = idx->dp;
   args.kappa = kappa;
   args.cap = p.cap;
 
@@ -414,7 +423,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     args.stride = (int)p.levels[li];
     args.xcd_map = sh.xcd_map;
     if (p.has_dense && li == 0) {
-      s = dispatch_fmt<kDense>(fmt, idx->dp, sh, args, st);
+      s = dispatch_fmt<kDense>(fmt, p.dp, sh, args, st);
       if (s == GV_OK)
         hipLaunchKernelGGL(k_dense_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, dense, m, p.ns, kappa,
                            seed);
@@ -425,7 +434,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
       return GV_EDEVICE;
     }
     if (last) profile_mark(st, 0, true);
-    s = dispatch_fmt<kFilter>(fmt, idx->dp, sh, args, st);
+    s = dispatch_fmt<kFilter>(fmt, p.dp, sh, args, st);
     if (last) profile_mark(st, 0, false);
     if (s != GV_OK) break;
     if (last) {
@@ -446,11 +455,11 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
 }  // namespace
 
 gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t, int64_t m, int kappa,
-                          int32_t* cand_ids, float* cand_scores, hipStream_t st) {
+                          int32_t* cand_ids, float* cand_scores, hipStream_t st, int d_search) {
   if (m == 0) return GV_OK;
   keep_pool(idx->device);
   ScanPlan p;
-  GV_TRY(plan_scan(idx, m, kappa, &p));
+  GV_TRY(plan_scan(idx, m, kappa, &p, d_search));
   uint8_t* ws = nullptr;
   if (hipMallocAsync((void**)&ws, std::max<size_t>(p.bytes, 256), st) != hipSuccess) {
     set_error("search scratch allocation failed");
@@ -464,14 +473,21 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
 // ---------------------------------------------------------------------------- whole search
 // Scratch of one search (S1 views and scales, S2/S3 lists, candidates), carved
 // from one workspace so the sequence runs without allocations.
-gv_status search_plan(const gv_model* model, const gv_index* idx, int64_t m, int kappa, SearchPlan* sp) {
+gv_status search_plan(const gv_model* model, const gv_index* idx, int64_t m, int kappa, SearchPlan* sp,
+                      int d_search, bool stored) {
   ScanPlan p;
-  GV_TRY(plan_scan(idx, m, kappa, &p));
+  GV_TRY(plan_scan(idx, m, kappa, &p, d_search));
+  if (!stored && !idx->X) {
+    set_error("the index keeps no full-dimension vectors: rerank from the stored vectors");
+    return GV_EINVAL;
+  }
+  sp->d_search = d_search;
+  sp->stored = stored;
   const size_t C = idx->C, dp = idx->dp, eb = fmt_bytes(idx->fmt);
   size_t o = 0;
   sp->off_t = o;    o = align256(o + sizeof(float) * m * C);
   sp->off_qc = o;   o = align256(o + sizeof(float) * m * C * dp);
-  sp->off_qhat = o; o = align256(o + eb * m * C * dp);
+  sp->off_qhat = o; o = align256(o + eb * m * C * p.dp);
   sp->off_cand = o; o = align256(o + sizeof(int32_t) * m * kappa);
   sp->off_csc = o;  o = align256(o + sizeof(float) * m * kappa);
   sp->off_scan = o; o = align256(o + p.bytes);
@@ -485,15 +501,18 @@ gv_status search_run(const gv_model* model, const gv_index* idx, const float* Q,
   if (m == 0) return GV_OK;
   uint8_t* ws = (uint8_t*)workspace;
   ScanPlan p;
-  GV_TRY(plan_scan(idx, m, kappa, &p));
+  GV_TRY(plan_scan(idx, m, kappa, &p, sp.d_search));
   float* t = (float*)(ws + sp.off_t);
   float* qc = (float*)(ws + sp.off_qc);
   void* qhat = ws + sp.off_qhat;
   int32_t* cand = (int32_t*)(ws + sp.off_cand);
   float* csc = (float*)(ws + sp.off_csc);
-  GV_TRY(project_impl(model, idx->fmt, Q, m, qc, t, qhat, st));
+  GV_TRY(project_impl(model, idx->fmt, Q, m, qc, t, qhat, st, sp.d_search));
   GV_TRY(run_scan(idx, p, ws + sp.off_scan, qhat, t, m, kappa, cand, csc, st));
-  GV_TRY(rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st));
+  if (sp.stored)
+    GV_TRY(rerank_stored_impl(idx, qc, m, cand, kappa, k, out_ids, out_scores, st));
+  else
+    GV_TRY(rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st));
   return GV_OK;
 }
 
@@ -503,6 +522,9 @@ namespace {
 // One workgroup per query, sixteen wavefronts; each wavefront scores four
 // candidate rows at a time so their loads are in flight together.
 constexpr int kRerankThreads = 1024;
+
+__device__ void sort_emit(double* s_score, int32_t* s_id, int64_t q, int k, int32_t* __restrict__ out_ids,
+                          float* __restrict__ out_scores);
 
 __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restrict__ X, int64_t n, int D,
                                                            const float* __restrict__ Q,
@@ -548,7 +570,14 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restri
     }
   }
   __syncthreads();
-  // bitonic sort of 256 (score, id) pairs: score desc, then id asc
+  sort_emit(s_score, s_id, q, k, out_ids, out_scores);
+}
+
+// bitonic sort of 256 (score, id) pairs in LDS (score desc, then id asc), then
+// the first k to the output row q; called by every thread of the workgroup
+__device__ void sort_emit(double* s_score, int32_t* s_id, int64_t q, int k, int32_t* __restrict__ out_ids,
+                          float* __restrict__ out_scores) {
+  const int tid = threadIdx.x;
   for (int size = 2; size <= 256; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       if (tid < 256) {
@@ -575,7 +604,86 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restri
   }
 }
 
+// Rerank from the stored vectors (Section 3.3): <A_c q, x'> with x' = s_c x^
+// over every stored coordinate, FP64 accumulation of exact products.  One
+// workgroup per query; a wavefront scores one candidate at a time, each lane
+// taking whole operand groups (EPL consecutive coordinates) of the candidate's
+// row from its 32-row tile.
+template <int FMT>
+__global__ __launch_bounds__(kRerankThreads) void k_rerank_stored(
+    const uint8_t* __restrict__ xlow, int dps, const float* __restrict__ scale, const uint8_t* __restrict__ tags,
+    const int32_t* __restrict__ pos, int64_t n, int C, const float* __restrict__ qc,
+    const int32_t* __restrict__ cand, int kappa, int k, int32_t* __restrict__ out_ids,
+    float* __restrict__ out_scores) {
+  __shared__ double s_score[256];
+  __shared__ int32_t s_id[256];
+  constexpr int W = kRerankThreads / 64;
+  constexpr int EPL = FMT == GV_FP32 ? 1 : 8, KM = FMT == GV_FP32 ? 2 : 16;
+  constexpr int EB = FMT == GV_FP32 ? 4 : (FMT == GV_FP8_E4M3 ? 1 : 2);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t q = blockIdx.x;
+  if (tid < 256) {
+    s_score[tid] = -INFINITY;
+    s_id[tid] = 0x7fffffff;
+  }
+  __syncthreads();
+  const int groups = dps / EPL;
+  for (int r = wave; r < kappa; r += W) {
+    const int32_t id = cand[q * kappa + r];
+    if (id < 0 || id >= n) continue;  // a missing candidate is skipped
+    const int c = tags[id];
+    const int64_t p = pos[id];
+    const int64_t t = p / kTileRows;
+    const int i = (int)(p - t * kTileRows);
+    const float* qv = qc + (q * C + c) * (int64_t)dps;
+    double acc = 0.0;
+    for (int g = lane; g < groups; g += 64) {
+      const int s = g * EPL / KM, half = (g * EPL % KM) / EPL;
+      const int64_t off = ((t * (dps / KM) + s) * 64 + i + kTileRows * half) * EPL;  // in elements
+      const uint8_t* src = xlow + off * EB;
+      if constexpr (FMT == GV_FP32) {
+        acc += (double)*(const float*)src * (double)qv[g];
+      } else if constexpr (FMT == GV_FP8_E4M3) {
+        const uint2 w = *(const uint2*)src;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          acc += from_fp8((uint8_t)(((e < 4 ? w.x : w.y) >> (8 * (e & 3))) & 255)) * (double)qv[g * 8 + e];
+      } else {
+        const uint4 w = *(const uint4*)src;
+        const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint16_t b = (uint16_t)((ww[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+          acc += (FMT == GV_FP16 ? from_fp16(b) : from_bf16(b)) * (double)qv[g * 8 + e];
+        }
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) {
+      s_score[r] = acc * (double)scale[c];  // exact: s_c is a power of two
+      s_id[r] = id;
+    }
+  }
+  __syncthreads();
+  sort_emit(s_score, s_id, q, k, out_ids, out_scores);
+}
+
 }  // namespace
+
+gv_status rerank_stored_impl(const gv_index* idx, const float* qc, int64_t m, const int32_t* cand, int kappa, int k,
+                             int32_t* out_ids, float* out_scores, hipStream_t st) {
+  if (m == 0) return GV_OK;
+  const dim3 g((unsigned)m), b(kRerankThreads);
+  const uint8_t* xl = (const uint8_t*)idx->xlow;
+  switch (idx->fmt) {
+    case GV_FP32: hipLaunchKernelGGL(k_rerank_stored<GV_FP32>, g, b, 0, st, xl, idx->dp, idx->scale, idx->tags, idx->pos, idx->n, idx->C, qc, cand, kappa, k, out_ids, out_scores); break;
+    case GV_FP16: hipLaunchKernelGGL(k_rerank_stored<GV_FP16>, g, b, 0, st, xl, idx->dp, idx->scale, idx->tags, idx->pos, idx->n, idx->C, qc, cand, kappa, k, out_ids, out_scores); break;
+    case GV_BF16: hipLaunchKernelGGL(k_rerank_stored<GV_BF16>, g, b, 0, st, xl, idx->dp, idx->scale, idx->tags, idx->pos, idx->n, idx->C, qc, cand, kappa, k, out_ids, out_scores); break;
+    default: hipLaunchKernelGGL(k_rerank_stored<GV_FP8_E4M3>, g, b, 0, st, xl, idx->dp, idx->scale, idx->tags, idx->pos, idx->n, idx->C, qc, cand, kappa, k, out_ids, out_scores); break;
+  }
+  GV_HIP(hipGetLastError());
+  return GV_OK;
+}
 
 gv_status rerank_impl(const gv_index* idx, const float* Q, int64_t m, const int32_t* cand, int kappa, int k,
                       int32_t* out_ids, float* out_scores, hipStream_t st) {

@@ -44,7 +44,7 @@ constexpr int kRows = kTileRows;
 enum Mode { kFilter = 0, kDense = 1 };
 
 struct ScoreArgs {
-  const uint8_t* xlow;     // operand tiles, n_pad x dp elements
+  const uint8_t* xlow;     // operand tiles, n_pad x dps elements; the scan reads the leading dp of each row
   const int32_t* ids;      // stored row -> original id (-1: padding)
   const float* scale;      // C
   const int64_t* offsets;  // C + 1 padded segment starts (stored rows)
@@ -57,6 +57,7 @@ struct ScoreArgs {
   float* dense;            // kDense: m x ns scores (ns = sampled tiles * 32)
   int64_t m, n_pad;
   int C, dp, kappa, R, nqb, cap;
+  int dps;      // stored (padded) row length: tiles are 32 * dps elements apart
   int stride;   // scan every stride-th tile
   int xcd_map;  // 1: workgroups sharing rows are pinned to one XCD
 };
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
     lbase[nb] = ((q < a.m ? q : 0) * a.R + r) * (int64_t)a.cap;
   }
 
-  const int64_t tile_bytes = (int64_t)kRows * a.dp * Op::EB;
+  const int64_t tile_bytes = (int64_t)kRows * a.dps * Op::EB;
   const int64_t kblock = 64 * Op::EPL * Op::EB;
   const uint8_t* xl = a.xlow + (int64_t)lane * Op::EPL * Op::EB;
 
@@ -482,8 +483,8 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
     // matrix-core chain of one tile with the maxima of the previous tile's
     // scores (Pv) computed between its steps: the vector ALU work runs while
     // the matrix core is busy instead of after it
-    auto mma_tile_max = [&](const S (&src)[KS], f32x16 (&A)[NB], const f32x16 (&Pv)[NB], float (&mx)[NB])
-        __attribute__((always_inline)) {
+    auto mma_tile_max = [&](S (&src)[KS], f32x16 (&A)[NB], const f32x16 (&Pv)[NB], float (&mx)[NB],
+                            const uint8_t* refill) __attribute__((always_inline)) {
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
         constexpr int nb = decltype(nbc)::value;
         A[nb] = f32x16{0};
@@ -496,6 +497,8 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           constexpr int nb = decltype(nbc)::value;
           A[nb] = Op::mma(av, bq[nb][st_], A[nb]);
         });
+        // this k-step's operand is consumed: its registers take the next tile's
+        if constexpr (WGT) src[st_] = *(const S*)(refill + st_ * kblock_c);
         constexpr int j0 = 1 + st_ * 15 / KS, j1 = 1 + (st_ + 1) * 15 / KS;
         Unroll<j0, j1>::run([&](auto jc) __attribute__((always_inline)) {
           constexpr int j = decltype(jc)::value;
@@ -505,9 +508,12 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           });
         });
       });
-      Unroll<0, KS * NB>::run([&](auto) __attribute__((always_inline)) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core op
-        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then up to two vector ALU ops
+      Unroll<0, KS>::run([&](auto) __attribute__((always_inline)) {
+        Unroll<0, NB>::run([&](auto) __attribute__((always_inline)) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core op
+          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then up to two vector ALU ops
+        });
+        if constexpr (WGT) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // the refill of the k-step
       });
     };
     auto mma_tile = [&](const S (&src)[KS], f32x16 (&A)[NB]) __attribute__((always_inline)) {
@@ -524,55 +530,70 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
 
     if constexpr (WGT) {
       // ---- tiles shared by the workgroup through an LDS ring of PL tiles.  Each
-      // wavefront copies every fourth 1 KiB chunk of a tile straight to LDS;
-      // after its own copies land (memory counter) and a barrier, every
-      // wavefront reads the whole tile from LDS.  Vector memory operations
-      // complete in order, so the wait counts the copies issued after this
-      // tile's, whatever stores happen in between.
+      // wavefront copies every fourth 1 KiB chunk of a tile straight to LDS
+      // (asm copies: the compiler does not order LDS reads behind them); after
+      // its own copies of a tile land (memory counter) and a barrier, every
+      // wavefront may read the whole tile.  Vector memory operations complete
+      // in order, so a wait counts the copies issued after the tile's, whatever
+      // stores happen in between.  The reads of tile t + 1 go out before the
+      // matrix-core chain of tile t and land while it runs.
       static_assert(TB % 1024 == 0, "tiles are copied in 1 KiB chunks");
       constexpr int NCH = TB / 1024;
       constexpr int SH_HI = (NCH + 3) / 4, SH_LO = NCH / 4;
-      const bool hi = wave < (NCH & 3);
-      // LDS byte address of this lane's operands in ring slot 0
-      const uint32_t ring_lds =
-          (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t*)s_ring) + lane * Op::EPL * Op::EB;
+      static_assert(PL >= 3, "the ring holds the tile in use, the next one and one in flight");
+      const int wv = __builtin_amdgcn_readfirstlane(wave);  // this wavefront's index, in a scalar register
+      const bool hi = wv < (NCH & 3);
+      const uint32_t ring_lds = (uint32_t)(uintptr_t)((__attribute__((address_space(3))) uint8_t*)s_ring);
+      const uint8_t* ring_lane = s_ring + lane * Op::EPL * Op::EB;  // this lane's operands in slot 0
       int slot_in = 0;  // ring slot of the next tile to copy
       auto issue = [&](int64_t vv) __attribute__((always_inline)) {
         const int64_t vc = vv < v1 ? vv : v1 - 1;
         const uint8_t* g = a.xlow + vc * stride * tile_bytes + (int64_t)lane * 16;
-        uint8_t* ls = s_ring + slot_in * TB;
-#pragma unroll
-        for (int j = wave; j < NCH; j += 4)
-          __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + j * 1024),
-                                           (__attribute__((address_space(3))) void*)(ls + j * 1024), 16, 0, 0);
+        const uint32_t ls = ring_lds + (uint32_t)(slot_in * TB);
+        Unroll<0, SH_HI>::run([&](auto kc) __attribute__((always_inline)) {
+          const int j = wv + 4 * decltype(kc)::value;
+          if (j < NCH) copy_lds16(g + j * 1024, ls + (uint32_t)(j * 1024));
+        });
         slot_in = slot_in + 1 == PL ? 0 : slot_in + 1;
       };
-      auto arrive = [&]() __attribute__((always_inline)) {
-        if (hi) wait_vm<(PL - 2) * SH_HI>(); else wait_vm<(PL - 2) * SH_LO>();
+      // own copies of a tile have landed while those of `later` newer tiles may
+      // still be in flight; then the barrier makes every wavefront's copies visible
+      auto arrive = [&](auto laterc) __attribute__((always_inline)) {
+        constexpr int later = decltype(laterc)::value;
+        if (hi) wait_vm<later * SH_HI>(); else wait_vm<later * SH_LO>();
         block_barrier();
       };
       Unroll<0, PL - 1>::run([&](auto pc) __attribute__((always_inline)) { issue(v0 + decltype(pc)::value); });
+      arrive(std::integral_constant<int, PL - 2>{});
       f32x16 acc0[NB], acc1[NB];
       S cur[KS];
-      int slot_rd = 0;  // ring slot of the tile to score
+#pragma unroll
+      for (int s = 0; s < KS; ++s) cur[s] = *(const S*)(ring_lane + s * kblock_c);
+      int slot_rd = 1;  // ring slot of the next tile
       for (int64_t vb = v0; vb < v1; vb += 2) {
         Unroll<0, 2>::run([&](auto uc) __attribute__((always_inline)) {
           constexpr int u = decltype(uc)::value;
           const int64_t vt = vb + u;
           if (vt >= v1) return;
-          arrive();
-          // the whole tile into registers first (one wait inside the read),
-          // then the next copy into the slot of tile vt - 1, which every
-          // wavefront finished reading before the barrier
-          LdsTile<KS, Op::EPL * Op::EB>::read(cur, ring_lds + slot_rd * TB);
+          if (vt + 1 < v1) {
+            // tile vt + 1 has landed once the copies of at most PL - 3 newer
+            // tiles are in flight; after the barrier every wavefront is done
+            // with tile vt - 1, whose slot takes the next copy
+            arrive(std::integral_constant<int, PL - 3>{});
+            issue(vt + PL - 1);
+          }
+          // the matrix-core chain of tile vt refills each k-step's operand from
+          // tile vt + 1 (after the last tile the reads are discarded)
+          const uint8_t* nxt = ring_lane + slot_rd * TB;
           slot_rd = slot_rd + 1 == PL ? 0 : slot_rd + 1;
-          issue(vt + PL - 1);
           if constexpr (MODE == kFilter) {
             float mx[NB];
-            if constexpr (u & 1) mma_tile_max(cur, acc1, acc0, mx); else mma_tile_max(cur, acc0, acc1, mx);
+            if constexpr (u & 1) mma_tile_max(cur, acc1, acc0, mx, nxt); else mma_tile_max(cur, acc0, acc1, mx, nxt);
             if constexpr (u & 1) filter(acc0, vt - 1, real_end, mx, vt > v0); else filter(acc1, vt - 1, real_end, mx, vt > v0);
           } else {
             if constexpr (u & 1) mma_tile(cur, acc1); else mma_tile(cur, acc0);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) cur[s] = *(const S*)(nxt + s * kblock_c);
             if (vt > v0) {
               if constexpr (u & 1) epilogue(acc0, vt - 1, real_end); else epilogue(acc1, vt - 1, real_end);
             }
@@ -600,7 +621,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           if constexpr (DEFER && MODE == kFilter) {
             // matrix core on tile vt, beside it the maxima of tile vt - 1, then its filter
             float mx[NB];
-            if constexpr (u & 1) mma_tile_max(ring[u % P], acc1, acc0, mx); else mma_tile_max(ring[u % P], acc0, acc1, mx);
+            if constexpr (u & 1) mma_tile_max(ring[u % P], acc1, acc0, mx, nullptr); else mma_tile_max(ring[u % P], acc0, acc1, mx, nullptr);
             const bool valid = (u > 0 || vt > v0) && vt - 1 < v1;
             if constexpr (u & 1) filter(acc0, vt - 1, real_end, mx, valid); else filter(acc1, vt - 1, real_end, mx, valid);
           } else if constexpr (DEFER) {

@@ -45,7 +45,8 @@ def reduced_score_tolerance(out, index, K: int) -> np.ndarray:
         a, b = index.offsets[c], index.offsets[c + 1]
         if a == b:
             continue
-        absdot = np.abs(out["qh"][:, c, :]) @ np.abs(index.xq[a:b]).T
+        ds = out["qh"].shape[2]  # leading coordinates scored (all of them unless flexible d)
+        absdot = np.abs(out["qh"][:, c, :]) @ np.abs(index.xq[a:b, :ds]).T
         tol[:, a:b] = (K + 2) * U32 * absdot * (index.scale[c] * out["t"][:, c])[:, None]
     return tol + np.abs(out["scores"]) * U32
 

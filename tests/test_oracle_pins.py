@@ -526,3 +526,73 @@ def test_search_full_dimension_recovers_exact_topk():
         if gs[qi, 9] - gs[qi, 10] > 1e-4 * abs(gs[qi, 0]):
             assert set(out["ids"][qi].tolist()) == set(gt[qi, :10].tolist())
         assert np.allclose(out["cand_scores"][qi], np.sort(out["out_scores"][qi])[::-1], rtol=1e-5, atol=1e-5)
+
+
+# ----------------------------------------------------------------------------- flexible d (Section 3.3)
+
+def test_flex_leading_coordinates_equal_refit_at_smaller_d():
+    """Searching the leading 3 of 8 stored coordinates is the search of the model fitted
+    at d = 3 (Section 3.3 with the nesting of Section 3.1): same views, same reduced
+    scores up to FP32 rounding of the stored rows, same final top-k."""
+    model8, X, Q = _small_problem("fp32", seed=30)
+    rng = np.random.default_rng(30)
+    QL = _lowrank_data(rng, 400, X.shape[1]).astype(np.float32)
+    model8 = G.fit(X, QL, 8, 4, seed=2)
+    model3 = G.fit(X, QL, 3, 4, seed=2)
+    assert not model8.fallback.any()
+    assert np.allclose(model8.A[:, :3], model3.A, atol=1e-12) and np.allclose(model8.B[:, :3], model3.B, atol=1e-12)
+    i8 = G.encode(model8.mu, model8.B, X, "fp32")
+    i3 = G.encode(model3.mu, model3.B, X, "fp32")
+    assert np.array_equal(i8.ids, i3.ids) and np.allclose(i8.xq[:, :3], i3.xq, rtol=2 ** -22, atol=0)
+    k, kappa = 5, 40
+    f = G.search_flex(i8, model8.A, Q, k, kappa, 3, "full")
+    r = G.search(i3, model3.A, Q, k, kappa)
+    assert np.allclose(f["qh"], r["qh"], rtol=2 ** -22, atol=0)
+    assert np.allclose(f["cand_scores"], r["cand_scores"], rtol=1e-6, atol=1e-9)
+    assert np.array_equal(f["ids"], r["ids"])
+
+
+def test_flex_stored_rerank_at_full_dimension_is_exact():
+    """Section 3.3: with d_s = D the stored vectors give undistorted similarities,
+    <A' q, x'> = <q, x> (A'^T B' = I when K_Q has full rank), cluster by cluster."""
+    rng = np.random.default_rng(31)
+    D = 12
+    means = G.normalise_rows(rng.standard_normal((2, D))) * 2
+    X = np.concatenate([_lowrank_data(rng, 600, D, mean=means[c]) for c in range(2)]).astype(np.float32)
+    Q = _lowrank_data(rng, 6, D).astype(np.float32)
+    model = G.fit(X, _lowrank_data(rng, 300, D), D, 2, seed=5)
+    idx = G.encode(model.mu, model.B, X, "fp32")
+    out = G.search_flex(idx, model.A, Q, 5, 30, 4, "stored")
+    for qi in range(Q.shape[0]):
+        ci = out["cand_ids"][qi]
+        got = G.rerank_stored(idx, out["qc"], qi, ci)
+        exact = X[ci].astype(np.float64) @ Q[qi].astype(np.float64)
+        assert np.allclose(got, exact, rtol=1e-5, atol=1e-5 * np.abs(exact).max())
+        assert np.array_equal(out["ids"][qi], G.topk(got, ci, 5)[0])
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "fp16", "fp8"])
+def test_flex_stages_against_brute_force(fmt):
+    """Leading-coordinate scores and the stored rerank by plain loops over Eq. 11 and
+    the Section 3.3 identity."""
+    model, X, Q = _small_problem(fmt, seed=32)
+    idx = G.encode(model.mu, model.B, X, fmt)
+    ds, k, kappa = 5, 4, 30
+    out = G.search_flex(idx, model.A, Q, k, kappa, ds, "stored")
+    n = X.shape[0]
+    pos_of = np.empty(n, np.int64); pos_of[idx.ids] = np.arange(n)
+    qc_exact = np.einsum("cjD,mD->mcj", model.A, Q.astype(np.float64))
+    assert np.allclose(out["qc"], qc_exact, rtol=2 ** -23, atol=0) and out["qc"].shape[2] == model.d
+    for qi in range(Q.shape[0]):
+        amax = np.abs(out["qc"][qi, :, :ds]).max(axis=1)
+        assert np.array_equal(out["t"][qi], formats.pow2_scale(fmt, amax))
+        s = np.empty(n)
+        for i in range(n):
+            c = idx.tags[i]
+            p = pos_of[i]
+            s[i] = idx.scale[c] * out["t"][qi, c] * sum(out["qh"][qi, c, j] * idx.xq[p, j] for j in range(ds))
+        want = sorted(range(n), key=lambda i: (-s[i], i))[:kappa]
+        assert out["cand_ids"][qi].tolist() == want
+        st = {i: sum(out["qc"][qi, idx.tags[i], j] * idx.xq[pos_of[i], j] * idx.scale[idx.tags[i]]
+                     for j in range(model.d)) for i in want}
+        assert out["ids"][qi].tolist() == sorted(want, key=lambda i: (-st[i], i))[:k]
