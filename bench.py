@@ -42,7 +42,7 @@ DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp8": "fp8-e4m3 (f16 mat
 # sources of the scanning kernel: a traffic record taken on other sources is stale
 KERNEL_SOURCES = ["paper_2410_22347_amd/csrc/search_kernels.hpp", "paper_2410_22347_amd/csrc/search_common.hpp",
                   "paper_2410_22347_amd/csrc/common.hpp", "paper_2410_22347_amd/csrc/scan_fp16.hip",
-                  "paper_2410_22347_amd/csrc/search.hip"]
+                  "paper_2410_22347_amd/csrc/search.hip", "paper_2410_22347_amd/csrc/lds_tile.hpp"]
 
 
 def log(*a):

@@ -266,6 +266,29 @@ gv_status gv_score_topk(const gv_index* index, const void* qhat, const float* t,
 gv_status gv_rerank(const gv_index* index, const float* Q, int64_t m, const int32_t* cand_ids,
                     int32_t kappa, int32_t k, int32_t* out_ids, float* out_scores, void* stream);
 
+/* ------------------------------------------------------------------ Euclidean distance */
+
+/* What gv_augment appends. */
+enum {
+  GV_AUG_DATABASE = 0,  /* -||v||^2 / 2 */
+  GV_AUG_QUERY = 1      /* 1 */
+};
+
+/*
+ * gv_augment -- one appended coordinate that turns Euclidean nearest
+ * neighbours into maximum inner products (the paper's appendix on adapting
+ * other similarities): x^ = [x, -||x||^2 / 2] for database vectors,
+ * q^ = [q, 1] for queries, so <q^, x^> = -||q - x||^2 / 2 + ||q||^2 / 2.
+ * Fit, encode and search then run unchanged on the D + 1 dimensional vectors.
+ *
+ * V    device n x D FP32.  out  device n x (D + 1) FP32 (must not alias V):
+ *      row i is V's row i followed by the appended value, which for the
+ *      database is the FP64 sum of the exact squares times -1/2, rounded once
+ *      to FP32.
+ * Errors: GV_EINVAL, GV_EDEVICE.
+ */
+gv_status gv_augment(const float* V, int64_t n, int32_t D, int32_t kind, float* out, void* stream);
+
 /* ------------------------------------------------------------------ flexible d */
 
 /* Rerank source of gv_search_flex. */
@@ -335,8 +358,9 @@ gv_status gv_rerank_stored(const gv_index* index, const float* qc, int64_t m, co
  * thread's following searches (0 restores the automatic choice):
  * splits = row ranges per query block (1..4096), qpw = queries per wavefront
  * (32, 64 or 128), cap = key slots per (query, row range) list; a list is
- * compacted to its kappa best when it may overflow before the next check
- * (512..2048; a search with cap < kappa + 417 fails with GV_EINVAL).  Results
+ * compacted to its kappa best (ties at the kappa-th score kept) when it may
+ * overflow before the next check (512..2048; a search with cap < kappa + 417
+ * fails with GV_EINVAL).  Results
  * do not depend on these; only speed does.  Errors: GV_EINVAL.
  */
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap);

@@ -335,6 +335,26 @@ def search(index: Index, A: np.ndarray, Q: np.ndarray, k: int, kappa: int):
                 ids=out_ids, out_scores=out_sc)
 
 
+# ============================================================================ Euclidean distance
+# Appendix (adapting other similarities): nearest neighbours under the Euclidean
+# distance become maximum inner products after appending one coordinate,
+# x^ = [x, -||x||^2 / 2] and q^ = [q, 1], since <q^, x^> = <q, x> - ||x||^2 / 2
+# differs from -||q - x||^2 / 2 by a term constant in x.
+
+def augment_database(X: np.ndarray) -> np.ndarray:
+    """[x, -||x||^2 / 2] per row; the norm in float64 from the FP32 values, the
+    appended value rounded once to FP32.  Returns FP32, n x (D + 1)."""
+    X32 = np.asarray(X, np.float32)
+    sq = np.sum(X32.astype(np.float64) ** 2, axis=1)
+    return np.concatenate([X32, formats.round_to("fp32", -0.5 * sq)[:, None].astype(np.float32)], axis=1)
+
+
+def augment_queries(Q: np.ndarray) -> np.ndarray:
+    """[q, 1] per row, FP32, m x (D + 1)."""
+    Q32 = np.asarray(Q, np.float32)
+    return np.concatenate([Q32, np.ones((Q32.shape[0], 1), np.float32)], axis=1)
+
+
 # ============================================================================ flexible d
 # Section 3.3: the stored vectors keep d_s >= d coordinates ordered by decreasing
 # eigenvalue of W K_X W (the rows of P come sorted that way), so a search may use

@@ -29,7 +29,7 @@ EXPORTED = [
     "gv_index_export", "gv_index_destroy", "gv_search", "gv_project", "gv_score_topk",
     "gv_rerank", "gv_search_tuning", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
     "gv_padded_dim", "gv_tags", "gv_moments", "gv_loss_grad", "gv_search_batched", "gv_batch_release",
-    "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored",
+    "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored", "gv_augment",
 ]
 
 
@@ -79,6 +79,7 @@ _sig("gv_project", [_vp, ctypes.c_int, _vp, _i64, _vp, _vp, _vp, _vp])
 _sig("gv_score_topk", [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp])
 _sig("gv_rerank", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_search_tuning", [_i32, _i32, _i32])
+_sig("gv_augment", [_vp, _i64, _i32, _i32, _vp, _vp])
 _sig("gv_search_flex", [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_project_flex", [_vp, ctypes.c_int, _vp, _i64, _i32, _vp, _vp, _vp, _vp])
 _sig("gv_score_topk_flex", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
@@ -227,6 +228,16 @@ def search(model: Model, index: Index, Q, k: int, kappa: int, with_scores: bool 
     sc = torch.empty((m, k), dtype=torch.float32, device=Q.device) if with_scores else None
     _check(_lib.gv_search(model._h, index._h, _ptr(Q), m, k, kappa, _ptr(ids), _ptr(sc), _stream()), "gv_search")
     return ids, sc
+
+
+def augment(V, kind: str):
+    """Euclidean adaptation: [v, -||v||^2 / 2] (kind "database") or [v, 1] ("query")."""
+    import torch
+    _dev_f32(V)
+    n, D = V.shape
+    out = torch.empty((n, D + 1), dtype=torch.float32, device=V.device)
+    _check(_lib.gv_augment(_ptr(V), n, D, {"database": 0, "query": 1}[kind], _ptr(out), _stream()), "gv_augment")
+    return out
 
 
 RERANK = {"full": 0, "stored": 1}

@@ -463,6 +463,18 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
   });
 }
 
+// ---------------------------------------------------------------------------- Euclidean adaptation
+gv_status gv_augment(const float* V, int64_t n, int32_t D, int32_t kind, float* out, void* stream) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(n >= 0 && D >= 1, "gv_augment: need n >= 0 and D >= 1");
+    GV_REQUIRE(kind == GV_AUG_DATABASE || kind == GV_AUG_QUERY, "gv_augment: unknown kind");
+    if (n == 0) return GV_OK;
+    GV_REQUIRE(V && out, "gv_augment: NULL argument");
+    GV_REQUIRE((const void*)V != (const void*)out, "gv_augment: out must not alias V");
+    return augment_impl(V, n, D, kind == GV_AUG_DATABASE, out, (hipStream_t)stream);
+  });
+}
+
 // ---------------------------------------------------------------------------- flexible d (Section 3.3)
 static gv_status check_d_search(const gv_model* model, int32_t d_search) {
   GV_REQUIRE(d_search >= 1 && d_search <= model->d, "d_search must lie in [1, d]");

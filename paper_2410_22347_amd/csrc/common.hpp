@@ -244,6 +244,7 @@ gv_status rerank_impl(const gv_index* index, const float* Q, int64_t m, const in
 gv_status rerank_stored_impl(const gv_index* index, const float* qc, int64_t m, const int32_t* cand,
                              int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
 gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite);
+gv_status augment_impl(const float* V, int64_t n, int D, int database, float* out, hipStream_t st);
 gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* tags, hipStream_t st);
 gv_status moments_impl(const float* V, int64_t n, int D, const uint8_t* tags, int C, double* K, hipStream_t st);
 gv_status loss_grad_impl(int C, int d, int D, const float* A, const float* B, const double* KQ, const double* KX,

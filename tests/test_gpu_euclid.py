@@ -1,0 +1,91 @@
+"""Euclidean nearest neighbours through the augmentation of the paper's appendix
+on adapting other similarities, on the GPU through the C ABI: the appended
+coordinate against the oracle, then fit (oracle), encode and search of the
+augmented vectors against the oracle's search and brute-force distances."""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import problem
+from oracle import gleanvec as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_22347_amd as lib
+    return lib
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.mark.parametrize("n,D", [(1, 1), (5_003, 33), (2_000, 200)])
+def test_augment_matches_oracle(gv, n, D):
+    _say(f"[augment] n={n} D={D}")
+    rng = np.random.default_rng(50 + D)
+    V = (rng.standard_normal((n, D)) * rng.uniform(0.1, 4.0, (n, 1))).astype(np.float32)
+    got = gv.augment(dev(V), "database").cpu().numpy()
+    want = G.augment_database(V)
+    assert np.array_equal(got[:, :D], V)
+    last_g, last_w = got[:, D], want[:, D]
+    ulp = np.spacing(np.abs(last_w).astype(np.float32))
+    assert np.all(np.abs(last_g - last_w) <= ulp)      # one rounding of an FP64 sum on both sides
+    assert np.mean(last_g == last_w) > 0.999
+    q = gv.augment(dev(V), "query").cpu().numpy()
+    assert np.array_equal(q, G.augment_queries(V))
+
+
+def test_augment_argument_errors(gv):
+    V = dev(np.ones((3, 4), np.float32))
+    with pytest.raises(gv.GleanVecError):
+        gv._check(gv._lib.gv_augment(gv._ptr(V), 3, 4, 7, gv._ptr(V), None), "gv_augment")
+    with pytest.raises(gv.GleanVecError):
+        gv._check(gv._lib.gv_augment(gv._ptr(V), 3, 4, 0, gv._ptr(V), None), "gv_augment")
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "fp16"])
+def test_euclidean_search(gv, fmt):
+    """GPU augmentation, encode and search of the augmented vectors: the oracle's search
+    of its own augmented vectors agrees, and with FP32 storage at d = D + 1 the result
+    is the Euclidean top-k wherever the k-th gap is wide."""
+    from scipy.spatial.distance import cdist
+    _say(f"[euclid] {fmt}")
+    X, QL, Q = problem(121, 48, 4, 12_000, 1_500, 25, law="mixture")
+    rng = np.random.default_rng(121)
+    X = (X * rng.uniform(0.5, 2.0, (X.shape[0], 1))).astype(np.float32)  # unnormalised rows
+    d = 49 if fmt == "fp32" else 24
+    om = G.fit(G.augment_database(X), G.augment_queries(QL), d, 4, seed=3)
+    oi = G.encode(om.mu, om.B, G.augment_database(X), fmt)
+    kappa, k = 64, 10
+    out = G.search(oi, om.A, G.augment_queries(Q), k, kappa)
+    model = gv.model_import(om.mu, om.A, om.B)
+    Xa = gv.augment(dev(X), "database")
+    Qa = gv.augment(dev(Q), "query")
+    idx = gv.encode(model, Xa, fmt)
+    ids, sc = gv.search(model, idx, Qa, k, kappa)
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy()
+    same = np.mean([set(a.tolist()) == set(b.tolist()) for a, b in zip(ids, out["ids"])])
+    assert same >= 0.9, same
+    if fmt == "fp32":
+        dist = cdist(Q.astype(np.float64), X.astype(np.float64), "sqeuclidean")
+        checked = 0
+        for qi in range(Q.shape[0]):
+            order = np.argsort(dist[qi], kind="stable")
+            if dist[qi, order[k]] - dist[qi, order[k - 1]] > 1e-4 * dist[qi, order[k - 1]]:
+                assert set(ids[qi].tolist()) == set(order[:k].tolist()), f"q{qi}"
+                checked += 1
+        assert checked >= 10

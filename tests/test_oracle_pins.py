@@ -596,3 +596,55 @@ def test_flex_stages_against_brute_force(fmt):
         st = {i: sum(out["qc"][qi, idx.tags[i], j] * idx.xq[pos_of[i], j] * idx.scale[idx.tags[i]]
                      for j in range(model.d)) for i in want}
         assert out["ids"][qi].tolist() == sorted(want, key=lambda i: (-st[i], i))[:k]
+
+
+# ----------------------------------------------------------------------------- Euclidean adaptation (Appendix)
+
+def test_euclidean_augmentation_identity_and_nearest_neighbours():
+    """<q^, x^> = <q, x> - ||x||^2 / 2 (up to the one FP32 rounding of the appended
+    value), so the arg-max of the augmented inner product is the Euclidean nearest
+    neighbour: checked against scipy's distances by brute force."""
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(40)
+    X = (rng.standard_normal((500, 7)) * rng.uniform(0.2, 3.0, (500, 1))).astype(np.float32)
+    Q = rng.standard_normal((30, 7)).astype(np.float32)
+    Xa = G.augment_database(X)
+    Qa = G.augment_queries(Q)
+    assert Xa.dtype == np.float32 and Xa.shape == (500, 8) and np.array_equal(Xa[:, :7], X)
+    assert np.array_equal(Qa[:, :7], Q) and np.all(Qa[:, 7] == 1.0)
+    ip = Qa.astype(np.float64) @ Xa.astype(np.float64).T
+    want = Q.astype(np.float64) @ X.astype(np.float64).T - 0.5 * np.sum(X.astype(np.float64) ** 2, axis=1)
+    assert np.allclose(ip, want, rtol=0, atol=2 ** -24 * np.abs(want).max() * 2)
+    dist = cdist(Q.astype(np.float64), X.astype(np.float64), "sqeuclidean")
+    for qi in range(30):
+        order = np.argsort(dist[qi], kind="stable")
+        if dist[qi, order[1]] - dist[qi, order[0]] > 1e-4:
+            assert int(np.argmax(ip[qi])) == int(order[0])
+        # the whole ranking agrees where the gaps are wide
+        a = np.argsort(-ip[qi], kind="stable")[:10]
+        gaps = np.diff(dist[qi, order[:11]])
+        if np.all(gaps > 1e-4):
+            assert a.tolist() == order[:10].tolist()
+
+
+def test_euclidean_search_end_to_end():
+    """Fit, encode and search on augmented vectors (FP32 storage, d = D + 1): the
+    result is the Euclidean top-k where the k-th gap is wide."""
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(41)
+    D = 10
+    X = (_lowrank_data(rng, 1500, D) * rng.uniform(0.3, 2.0, (1500, 1))).astype(np.float32)
+    Q = _lowrank_data(rng, 15, D).astype(np.float32)
+    QL = _lowrank_data(rng, 300, D).astype(np.float32)
+    Xa, Qa, QLa = G.augment_database(X), G.augment_queries(Q), G.augment_queries(QL)
+    model = G.fit(Xa, QLa, D + 1, 2, seed=6)
+    idx = G.encode(model.mu, model.B, Xa, "fp32")
+    out = G.search(idx, model.A, Qa, 5, 40)
+    dist = cdist(Q.astype(np.float64), X.astype(np.float64), "sqeuclidean")
+    checked = 0
+    for qi in range(15):
+        order = np.argsort(dist[qi], kind="stable")
+        if dist[qi, order[5]] - dist[qi, order[4]] > 1e-3 * dist[qi, order[4]]:
+            assert set(out["ids"][qi].tolist()) == set(order[:5].tolist())
+            checked += 1
+    assert checked >= 8
