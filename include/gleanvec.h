@@ -406,6 +406,38 @@ gv_status gv_tags(const gv_model* model, const float* X, int64_t n, uint8_t* tag
 gv_status gv_moments(const float* V, int64_t n, int32_t D, const uint8_t* tags, int32_t C, double* K,
                      void* stream);
 
+/* ------------------------------------------------------------------ streaming */
+
+/*
+ * gv_moments_update -- streaming update of the statistics (Section 3,
+ * streaming vector search): K[c] += sign * sum over rows v of V with
+ * tags[i] == c of v v^T, FP64 accumulation of exact FP32 products.  sign +1
+ * for inserted vectors, -1 for removed ones (their tags as when inserted, e.g.
+ * from gv_tags).  Arguments otherwise as gv_moments; K is read and written.
+ * Synchronises `stream`.  Errors: GV_EINVAL (tag >= C, bad sizes, sign),
+ * GV_ENOMEM, GV_EDEVICE.
+ */
+gv_status gv_moments_update(const float* V, int64_t n, int32_t D, const uint8_t* tags, int32_t C,
+                            int32_t sign, double* K, void* stream);
+
+/*
+ * gv_fit_from_stats -- the projections of a model recomputed from statistics
+ * the caller keeps (Section 3, streaming vector search: the SVDs of
+ * Algorithm 2 replaced by the eigendecompositions of K_Q and W K_{X_c} W).
+ * mu      host C x D FP64 landmarks (kept from an earlier fit).
+ * KQ      device D x D FP64: sum of q q^T over m_q learn queries.
+ * KX      device C x D x D FP64: per-cluster sums of x x^T.
+ * counts  host C int64: vectors behind each K_{X_c}; a cluster with fewer
+ *         than d takes the projection of the pooled statistics.
+ * Builds W = K^{1/2} and W+ from K_Q / m_q, P_c = top-d eigenvectors of
+ * W K_{X_c} W, A_c = P_c W+, B_c = P_c W, exactly as gv_fit does after its
+ * statistics; gv_model_stats then reports these statistics (K_Q as a mean).
+ * Errors: GV_EINVAL, GV_ENONFINITE, GV_ENOMEM, GV_EDEVICE.
+ */
+gv_status gv_fit_from_stats(const double* mu, const double* KQ, double m_q, const double* KX,
+                            const int64_t* counts, int32_t C, int32_t d, int32_t D, void* stream,
+                            gv_model** out);
+
 /*
  * gv_loss_grad -- the inner-product approximation loss of Problem 3 summed
  * over clusters, and its gradient, through the second-moment rewrite of

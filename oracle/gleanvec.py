@@ -227,6 +227,16 @@ def fit(X_learn: np.ndarray, Q_learn: np.ndarray, d: int, C: int, seed: int,
     KQ = second_moment(Qm, mean=True)
     KX = np.stack([second_moment(X[tags == c], mean=False) for c in range(C)])
     counts = np.bincount(tags, minlength=C)
+    return projections_from_stats(mu, KQ, KX, counts, d, iters)
+
+
+def projections_from_stats(mu: np.ndarray, KQ: np.ndarray, KX: np.ndarray, counts: np.ndarray, d: int,
+                           iters: int = 0) -> Model:
+    """Per-cluster LeanVec-Sphering from the second-moment statistics (Section 3.2,
+    Algorithm 2 through eigendecompositions): KQ the mean of q q^T, KX the per-cluster
+    sums of x x^T; a cluster with fewer than d vectors takes the pooled projection."""
+    C, D = mu.shape
+    counts = np.asarray(counts, np.int64)
     W, Wp, lam_Q = sphering_W(KQ)
     A = np.empty((C, d, D))
     B = np.empty((C, d, D))
@@ -243,6 +253,29 @@ def fit(X_learn: np.ndarray, Q_learn: np.ndarray, d: int, C: int, seed: int,
         B[c] = P @ W
         lam_c[c] = lam
     return Model(mu, A, B, W, Wp, lam_Q, lam_c, counts, fallback, KQ, KX, iters)
+
+
+# ============================================================================ streaming
+# Section 3 (streaming vector search): the statistics are sums, so inserting or
+# removing x adds or subtracts x x^T; the projections are recomputed from them
+# (the SVDs of Algorithm 2 replaced by eigendecompositions) with the landmarks kept.
+
+def update_moments(K: np.ndarray, V: np.ndarray, tags: np.ndarray | None, sign: int) -> np.ndarray:
+    """K[c] + sign * sum_{v with tag c} v v^T, float64 (tags None: one cluster)."""
+    K = np.array(K, np.float64, copy=True)
+    V = np.asarray(V, np.float64)
+    tags = np.zeros(V.shape[0], np.int64) if tags is None else np.asarray(tags)
+    for c in range(K.shape[0]):
+        Vc = V[tags == c]
+        K[c] += sign * (Vc.T @ Vc)
+    return K
+
+
+def fit_from_stats(mu: np.ndarray, KQ_sum: np.ndarray, m_q: float, KX: np.ndarray, counts: np.ndarray,
+                   d: int) -> Model:
+    """The model of kept landmarks and statistics: K_Q = KQ_sum / m_q."""
+    return projections_from_stats(np.asarray(mu, np.float64), np.asarray(KQ_sum, np.float64) / m_q,
+                                  np.asarray(KX, np.float64), counts, d)
 
 
 # ============================================================================ encode

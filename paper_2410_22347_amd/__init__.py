@@ -30,6 +30,7 @@ EXPORTED = [
     "gv_rerank", "gv_search_tuning", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
     "gv_padded_dim", "gv_tags", "gv_moments", "gv_loss_grad", "gv_search_batched", "gv_batch_release",
     "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored", "gv_augment",
+    "gv_moments_update", "gv_fit_from_stats",
 ]
 
 
@@ -80,6 +81,8 @@ _sig("gv_score_topk", [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp])
 _sig("gv_rerank", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_search_tuning", [_i32, _i32, _i32])
 _sig("gv_augment", [_vp, _i64, _i32, _i32, _vp, _vp])
+_sig("gv_moments_update", [_vp, _i64, _i32, _vp, _i32, _i32, _vp, _vp])
+_sig("gv_fit_from_stats", [_vp, _vp, ctypes.c_double, _vp, _vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)])
 _sig("gv_search_flex", [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_project_flex", [_vp, ctypes.c_int, _vp, _i64, _i32, _vp, _vp, _vp, _vp])
 _sig("gv_score_topk_flex", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
@@ -421,6 +424,36 @@ def moments(V, tags_=None, C: int = 1):
     K = torch.empty((C, D, D), dtype=torch.float64, device=V.device)
     _check(_lib.gv_moments(_ptr(V), V.shape[0], D, _ptr(tags_), C, _ptr(K), _stream()), "gv_moments")
     return K
+
+
+def moments_update(K, V, tags_=None, sign: int = 1):
+    """Streaming update in place: K[c] += sign * sum_{tag == c} v v^T (sign +1 insert, -1 remove)."""
+    import torch
+    V = _dev_f32(V)
+    if tags_ is not None and not (tags_.is_cuda and tags_.dtype == torch.uint8 and tags_.is_contiguous()
+                                  and tags_.shape == (V.shape[0],)):
+        raise ValueError("tags must be a contiguous uint8 CUDA tensor with one entry per row")
+    if not (K.is_cuda and K.dtype == torch.float64 and K.is_contiguous() and K.dim() == 3):
+        raise ValueError("K must be a contiguous C x D x D float64 CUDA tensor")
+    _check(_lib.gv_moments_update(_ptr(V), V.shape[0], V.shape[1], _ptr(tags_), K.shape[0], sign, _ptr(K),
+                                  _stream()), "gv_moments_update")
+    return K
+
+
+def fit_from_stats(mu, KQ, m_q: float, KX, counts, d: int) -> Model:
+    """Projections recomputed from kept statistics (streaming updates): mu host C x D,
+    KQ device D x D sum over m_q queries, KX device C x D x D sums, counts host C."""
+    import torch
+    mu = np.ascontiguousarray(mu, np.float64)
+    counts = np.ascontiguousarray(counts, np.int64)
+    C, D = mu.shape
+    for t, shape in ((KQ, (D, D)), (KX, (C, D, D))):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
+            raise ValueError(f"statistics must be contiguous float64 CUDA tensors of shape {shape}")
+    h = _vp()
+    _check(_lib.gv_fit_from_stats(_np_ptr(mu), _ptr(KQ), float(m_q), _ptr(KX), _np_ptr(counts), C, d, D, _stream(),
+                                  ctypes.byref(h)), "gv_fit_from_stats")
+    return Model(h)
 
 
 def loss_grad(A, B, KQ, KX, n_pairs: float, grads: bool = True):

@@ -409,6 +409,40 @@ gv_status gv_moments(const float* V, int64_t n, int32_t D, const uint8_t* tags, 
   });
 }
 
+gv_status gv_moments_update(const float* V, int64_t n, int32_t D, const uint8_t* tags, int32_t C, int32_t sign,
+                            double* K, void* stream) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(n >= 0 && D >= 1 && C >= 1 && C <= 256, "gv_moments_update: bad sizes");
+    GV_REQUIRE(sign == 1 || sign == -1, "gv_moments_update: sign must be +1 or -1");
+    GV_REQUIRE(tags || C == 1 || n == 0, "gv_moments_update: C must be 1 without tags");
+    GV_REQUIRE(K && (V || n == 0), "gv_moments_update: NULL argument");
+    return moments_impl(V, n, D, tags, C, K, (hipStream_t)stream, sign);
+  });
+}
+
+gv_status gv_fit_from_stats(const double* mu, const double* KQ, double m_q, const double* KX, const int64_t* counts,
+                            int32_t C, int32_t d, int32_t D, void* stream, gv_model** out) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(out != nullptr, "gv_fit_from_stats: out is NULL");
+    *out = nullptr;
+    GV_REQUIRE(mu && KQ && KX && counts, "gv_fit_from_stats: NULL input");
+    GV_REQUIRE(D >= 1 && d >= 1 && d <= D, "gv_fit_from_stats: need 1 <= d <= D");
+    GV_REQUIRE(C >= 1 && C <= 255, "gv_fit_from_stats: need 1 <= C <= 255");
+    GV_REQUIRE(m_q > 0.0 && std::isfinite(m_q), "gv_fit_from_stats: m_q must be positive and finite");
+    if (!finite_host(mu, (size_t)C * D)) return GV_ENONFINITE;
+    for (int c = 0; c < C; ++c) GV_REQUIRE(counts[c] >= 0, "gv_fit_from_stats: negative count");
+    gv_model* m = nullptr;
+    GV_TRY(alloc_model(C, d, D, &m));
+    gv_status s = fit_from_stats_impl(mu, KQ, m_q, KX, counts, (hipStream_t)stream, m);
+    if (s != GV_OK) {
+      gv_model_destroy(m);
+      return s;
+    }
+    *out = m;
+    return GV_OK;
+  });
+}
+
 gv_status gv_loss_grad(int32_t C, int32_t d, int32_t D, const float* A, const float* B, const double* KQ,
                        const double* KX, double n_pairs, double* loss, float* dA, float* dB, void* stream) {
   return guarded([&]() -> gv_status {

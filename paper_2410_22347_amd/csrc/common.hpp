@@ -222,6 +222,10 @@ gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, 
                    uint64_t seed, const gv_fit_opts* opts, hipStream_t st, gv_model* model);
 gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt, hipStream_t st,
                       gv_index* index);
+gv_status sphere_project(gv_model* model, const double* KX_dev, const std::vector<int64_t>& counts,
+                         const double* mu_dev, hipStream_t st);
+gv_status fit_from_stats_impl(const double* mu, const double* KQ, double m_q, const double* KX,
+                              const int64_t* counts, hipStream_t st, gv_model* model);
 // d_search (0: all of the model's d) is the number of leading coordinates the
 // views and the scan use (Section 3.3); q_c always holds all d of them.
 gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m, float* qc,
@@ -246,7 +250,8 @@ gv_status rerank_stored_impl(const gv_index* index, const float* qc, int64_t m, 
 gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite);
 gv_status augment_impl(const float* V, int64_t n, int D, int database, float* out, hipStream_t st);
 gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* tags, hipStream_t st);
-gv_status moments_impl(const float* V, int64_t n, int D, const uint8_t* tags, int C, double* K, hipStream_t st);
+gv_status moments_impl(const float* V, int64_t n, int D, const uint8_t* tags, int C, double* K, hipStream_t st,
+                       int sign = 0);
 gv_status loss_grad_impl(int C, int d, int D, const float* A, const float* B, const double* KQ, const double* KX,
                          double n_pairs, double* loss, float* dA, float* dB, hipStream_t st);
 

@@ -163,6 +163,123 @@ void parallel_for(int count, F f) {
 
 }  // namespace
 
+// Sphering and per-cluster projections from the statistics (Section 3.2,
+// Algorithm 2 through eigendecompositions): W, W+ from model->KQ (the mean
+// second moment of the queries, host), P_c from W K_c W with K_c = KX_dev
+// (device, C x D x D sums; model->KX holds the same on the host), then
+// A_c = P_c W+, B_c = P_c W.  A cluster with fewer than d vectors takes the
+// projection of the pooled statistics.  mu_dev: the C x D landmarks (device).
+gv_status sphere_project(gv_model* model, const double* KX_dev, const std::vector<int64_t>& counts,
+                         const double* mu_dev, hipStream_t st) {
+  const int C = model->C, d = model->d, D = model->D;
+  const size_t DD = (size_t)D * D;
+  DevBuf<double> W, Wp, tmp, Y;
+  // ------------------------------------------------ sphering: W, W+
+  std::vector<double> Aq(model->KQ), lamQ, Uq;
+  eigh_desc(D, Aq, lamQ, Uq);
+  const double rcond = (double)D * 0x1.0p-52;
+  std::vector<double> VS(DD), VSp(DD);
+  for (int r = 0; r < D; ++r) {
+    double s = std::sqrt(std::max(lamQ[r], 0.0));
+    double sp = (lamQ[0] > 0 && lamQ[r] > rcond * lamQ[0]) ? 1.0 / s : 0.0;
+    for (int j = 0; j < D; ++j) {
+      VS[(size_t)r * D + j] = s * Uq[(size_t)r * D + j];
+      VSp[(size_t)r * D + j] = sp * Uq[(size_t)r * D + j];
+    }
+  }
+  GV_TRY(W.alloc(DD));
+  GV_TRY(Wp.alloc(DD));
+  GV_TRY(tmp.alloc(DD * 3));
+  {
+    double* d_vs = tmp.p;
+    double* d_vsp = tmp.p + DD;
+    double* d_u = tmp.p + 2 * DD;
+    GV_HIP(hipMemcpyAsync(d_vs, VS.data(), sizeof(double) * DD, hipMemcpyHostToDevice, st));
+    GV_HIP(hipMemcpyAsync(d_vsp, VSp.data(), sizeof(double) * DD, hipMemcpyHostToDevice, st));
+    GV_HIP(hipMemcpyAsync(d_u, Uq.data(), sizeof(double) * DD, hipMemcpyHostToDevice, st));
+    // W(i, j) = sum_r S_r U(i, r) U(j, r), U(i, r) = Vt[r][i]
+    GemmOperand<double> a1{d_vs, D, nullptr, Layout::KMajor}, b1{d_u, D, nullptr, Layout::KMajor};
+    GV_TRY(gemm_f64<double, double>(D, D, D, a1, b1, Epi::StoreF64, GemmOut{W.p, D, 0, 0, nullptr}, st));
+    GemmOperand<double> a2{d_vsp, D, nullptr, Layout::KMajor};
+    GV_TRY(gemm_f64<double, double>(D, D, D, a2, b1, Epi::StoreF64, GemmOut{Wp.p, D, 0, 0, nullptr}, st));
+    GV_HIP(hipStreamSynchronize(st));
+  }
+
+  // ------------------------------------------------ per-cluster projections
+  std::vector<uint8_t> fallback(C);
+  bool any_fb = false;
+  for (int c = 0; c < C; ++c) {
+    fallback[c] = counts[c] < d ? 1 : 0;
+    any_fb |= fallback[c] != 0;
+  }
+  const int nY = C + (any_fb ? 1 : 0);
+  GV_TRY(Y.alloc(DD * nY));
+  DevBuf<double> Kpool;
+  if (any_fb) {
+    std::vector<double> pool(DD, 0.0);
+    for (int c = 0; c < C; ++c)
+      for (size_t e = 0; e < DD; ++e) pool[e] += model->KX[DD * c + e];
+    GV_TRY(Kpool.alloc(DD));
+    GV_HIP(hipMemcpyAsync(Kpool.p, pool.data(), sizeof(double) * DD, hipMemcpyHostToDevice, st));
+  }
+  GemmOperand<double> w_op{W.p, D, nullptr, Layout::RowMajor};
+  for (int c = 0; c < nY; ++c) {
+    const double* K = (c < C) ? KX_dev + DD * c : Kpool.p;
+    if (c < C && fallback[c]) continue;
+    // T = W K  (K symmetric: T(i, j) = sum_k W(i, k) K(j, k)), then Y = T W
+    GemmOperand<double> k_op{K, D, nullptr, Layout::RowMajor};
+    GV_TRY(gemm_f64<double, double>(D, D, D, w_op, k_op, Epi::StoreF64, GemmOut{tmp.p, D, 0, 0, nullptr}, st));
+    GemmOperand<double> t_op{tmp.p, D, nullptr, Layout::RowMajor};
+    GV_TRY(gemm_f64<double, double>(D, D, D, t_op, w_op, Epi::StoreF64, GemmOut{Y.p + DD * c, D, 0, 0, nullptr}, st));
+  }
+  std::vector<double> hY(DD * nY);
+  GV_HIP(hipMemcpyAsync(hY.data(), Y.p, sizeof(double) * DD * nY, hipMemcpyDeviceToHost, st));
+  GV_HIP(hipStreamSynchronize(st));
+
+  std::vector<double> P((size_t)C * d * D), lamc((size_t)C * D);
+  std::vector<std::vector<double>> lam_all(nY), P_all(nY);
+  std::vector<int> jobs;
+  for (int c = 0; c < nY; ++c)
+    if (c == C || !fallback[c]) jobs.push_back(c);
+  parallel_for((int)jobs.size(), [&](int ji) {
+    int c = jobs[ji];
+    std::vector<double> Ysym(DD);
+    const double* y = hY.data() + DD * c;
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) Ysym[(size_t)i * D + j] = 0.5 * (y[(size_t)i * D + j] + y[(size_t)j * D + i]);
+    std::vector<double> lam, Vt;
+    eigh_desc(D, Ysym, lam, Vt);
+    Vt.resize((size_t)d * D);
+    canonical_signs(Vt.data(), d, D);
+    lam_all[c] = std::move(lam);
+    P_all[c] = std::move(Vt);
+  });
+  for (int c = 0; c < C; ++c) {
+    int src = fallback[c] ? C : c;
+    std::copy(P_all[src].begin(), P_all[src].end(), P.begin() + (size_t)c * d * D);
+    std::copy(lam_all[src].begin(), lam_all[src].end(), lamc.begin() + (size_t)c * D);
+  }
+
+  // A = P W+, B = P W (W, W+ symmetric), all clusters in one product each
+  DevBuf<double> dP;
+  GV_TRY(dP.alloc((size_t)C * d * D));
+  GV_HIP(hipMemcpyAsync(dP.p, P.data(), sizeof(double) * C * d * D, hipMemcpyHostToDevice, st));
+  GemmOperand<double> p_op{dP.p, D, nullptr, Layout::RowMajor}, wp_op{Wp.p, D, nullptr, Layout::RowMajor};
+  GV_TRY(gemm_f64<double, double>((int64_t)C * d, D, D, p_op, wp_op, Epi::StoreF64,
+                                  GemmOut{model->A, D, 0, 0, nullptr}, st));
+  GV_TRY(gemm_f64<double, double>((int64_t)C * d, D, D, p_op, w_op, Epi::StoreF64,
+                                  GemmOut{model->B, D, 0, 0, nullptr}, st));
+  GV_HIP(hipMemcpyAsync(model->mu, mu_dev, sizeof(double) * C * D, hipMemcpyDeviceToDevice, st));
+  GV_HIP(hipStreamSynchronize(st));
+
+  model->lamQ = lamQ;
+  model->lamc = lamc;
+  model->counts = counts;
+  model->fallback = fallback;
+  model->fitted = true;
+  return GV_OK;
+}
+
 gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, int d, int C, uint64_t seed,
                    const gv_fit_opts* opts, hipStream_t st, gv_model* model) {
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 50;
@@ -301,7 +418,7 @@ gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, 
   counting_sort(tags, C, lperm, loff);
 
   // ------------------------------------------------ statistics (Section 3.2)
-  DevBuf<double> KQ, KX, W, Wp, tmp, Y;
+  DevBuf<double> KQ, KX;
   GV_TRY(KQ.alloc(DD));
   GV_TRY(KX.alloc(DD * C));
   {
@@ -327,112 +444,32 @@ gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, 
   GV_HIP(hipMemcpy(model->KX.data(), KX.p, sizeof(double) * DD * C, hipMemcpyDeviceToHost));
   for (auto& v : model->KQ) v /= (double)m;
 
-  // ------------------------------------------------ sphering: W, W+
-  std::vector<double> Aq(model->KQ), lamQ, Uq;
-  eigh_desc(D, Aq, lamQ, Uq);
-  const double rcond = (double)D * 0x1.0p-52;
-  std::vector<double> VS(DD), VSp(DD);
-  for (int r = 0; r < D; ++r) {
-    double s = std::sqrt(std::max(lamQ[r], 0.0));
-    double sp = (lamQ[0] > 0 && lamQ[r] > rcond * lamQ[0]) ? 1.0 / s : 0.0;
-    for (int j = 0; j < D; ++j) {
-      VS[(size_t)r * D + j] = s * Uq[(size_t)r * D + j];
-      VSp[(size_t)r * D + j] = sp * Uq[(size_t)r * D + j];
-    }
-  }
-  GV_TRY(W.alloc(DD));
-  GV_TRY(Wp.alloc(DD));
-  GV_TRY(tmp.alloc(DD * 3));
-  {
-    double* d_vs = tmp.p;
-    double* d_vsp = tmp.p + DD;
-    double* d_u = tmp.p + 2 * DD;
-    GV_HIP(hipMemcpyAsync(d_vs, VS.data(), sizeof(double) * DD, hipMemcpyHostToDevice, st));
-    GV_HIP(hipMemcpyAsync(d_vsp, VSp.data(), sizeof(double) * DD, hipMemcpyHostToDevice, st));
-    GV_HIP(hipMemcpyAsync(d_u, Uq.data(), sizeof(double) * DD, hipMemcpyHostToDevice, st));
-    // W(i, j) = sum_r S_r U(i, r) U(j, r), U(i, r) = Vt[r][i]
-    GemmOperand<double> a1{d_vs, D, nullptr, Layout::KMajor}, b1{d_u, D, nullptr, Layout::KMajor};
-    GV_TRY(gemm_f64<double, double>(D, D, D, a1, b1, Epi::StoreF64, GemmOut{W.p, D, 0, 0, nullptr}, st));
-    GemmOperand<double> a2{d_vsp, D, nullptr, Layout::KMajor};
-    GV_TRY(gemm_f64<double, double>(D, D, D, a2, b1, Epi::StoreF64, GemmOut{Wp.p, D, 0, 0, nullptr}, st));
-    GV_HIP(hipStreamSynchronize(st));
-  }
-
-  // ------------------------------------------------ per-cluster projections
   std::vector<int64_t> counts(C);
-  std::vector<uint8_t> fallback(C);
-  bool any_fb = false;
-  for (int c = 0; c < C; ++c) {
-    counts[c] = loff[c + 1] - loff[c];
-    fallback[c] = counts[c] < d ? 1 : 0;
-    any_fb |= fallback[c] != 0;
-  }
-  const int nY = C + (any_fb ? 1 : 0);
-  GV_TRY(Y.alloc(DD * nY));
-  DevBuf<double> Kpool;
-  if (any_fb) {
-    std::vector<double> pool(DD, 0.0);
-    for (int c = 0; c < C; ++c)
-      for (size_t e = 0; e < DD; ++e) pool[e] += model->KX[DD * c + e];
-    GV_TRY(Kpool.alloc(DD));
-    GV_HIP(hipMemcpyAsync(Kpool.p, pool.data(), sizeof(double) * DD, hipMemcpyHostToDevice, st));
-  }
-  GemmOperand<double> w_op{W.p, D, nullptr, Layout::RowMajor};
-  for (int c = 0; c < nY; ++c) {
-    const double* K = (c < C) ? KX.p + DD * c : Kpool.p;
-    if (c < C && fallback[c]) continue;
-    // T = W K  (K symmetric: T(i, j) = sum_k W(i, k) K(j, k)), then Y = T W
-    GemmOperand<double> k_op{K, D, nullptr, Layout::RowMajor};
-    GV_TRY(gemm_f64<double, double>(D, D, D, w_op, k_op, Epi::StoreF64, GemmOut{tmp.p, D, 0, 0, nullptr}, st));
-    GemmOperand<double> t_op{tmp.p, D, nullptr, Layout::RowMajor};
-    GV_TRY(gemm_f64<double, double>(D, D, D, t_op, w_op, Epi::StoreF64, GemmOut{Y.p + DD * c, D, 0, 0, nullptr}, st));
-  }
-  std::vector<double> hY(DD * nY);
-  GV_HIP(hipMemcpyAsync(hY.data(), Y.p, sizeof(double) * DD * nY, hipMemcpyDeviceToHost, st));
-  GV_HIP(hipStreamSynchronize(st));
-
-  std::vector<double> P((size_t)C * d * D), lamc((size_t)C * D);
-  std::vector<std::vector<double>> lam_all(nY), P_all(nY);
-  std::vector<int> jobs;
-  for (int c = 0; c < nY; ++c)
-    if (c == C || !fallback[c]) jobs.push_back(c);
-  parallel_for((int)jobs.size(), [&](int ji) {
-    int c = jobs[ji];
-    std::vector<double> Ysym(DD);
-    const double* y = hY.data() + DD * c;
-    for (int i = 0; i < D; ++i)
-      for (int j = 0; j < D; ++j) Ysym[(size_t)i * D + j] = 0.5 * (y[(size_t)i * D + j] + y[(size_t)j * D + i]);
-    std::vector<double> lam, Vt;
-    eigh_desc(D, Ysym, lam, Vt);
-    Vt.resize((size_t)d * D);
-    canonical_signs(Vt.data(), d, D);
-    lam_all[c] = std::move(lam);
-    P_all[c] = std::move(Vt);
-  });
-  for (int c = 0; c < C; ++c) {
-    int src = fallback[c] ? C : c;
-    std::copy(P_all[src].begin(), P_all[src].end(), P.begin() + (size_t)c * d * D);
-    std::copy(lam_all[src].begin(), lam_all[src].end(), lamc.begin() + (size_t)c * D);
-  }
-
-  // A = P W+, B = P W (W, W+ symmetric), all clusters in one product each
-  DevBuf<double> dP;
-  GV_TRY(dP.alloc((size_t)C * d * D));
-  GV_HIP(hipMemcpyAsync(dP.p, P.data(), sizeof(double) * C * d * D, hipMemcpyHostToDevice, st));
-  GemmOperand<double> p_op{dP.p, D, nullptr, Layout::RowMajor}, wp_op{Wp.p, D, nullptr, Layout::RowMajor};
-  GV_TRY(gemm_f64<double, double>((int64_t)C * d, D, D, p_op, wp_op, Epi::StoreF64,
-                                  GemmOut{model->A, D, 0, 0, nullptr}, st));
-  GV_TRY(gemm_f64<double, double>((int64_t)C * d, D, D, p_op, w_op, Epi::StoreF64,
-                                  GemmOut{model->B, D, 0, 0, nullptr}, st));
-  GV_HIP(hipMemcpyAsync(model->mu, mu.p, sizeof(double) * C * D, hipMemcpyDeviceToDevice, st));
-  GV_HIP(hipStreamSynchronize(st));
-
-  model->lamQ = lamQ;
-  model->lamc = lamc;
-  model->counts = counts;
-  model->fallback = fallback;
+  for (int c = 0; c < C; ++c) counts[c] = loff[c + 1] - loff[c];
+  GV_TRY(sphere_project(model, KX.p, counts, mu.p, st));
   model->iters = it;
-  model->fitted = true;
+  return GV_OK;
+}
+
+// The projections of a model from statistics kept by the caller (streaming
+// updates of Section 3: K_Q and K_{X_c} are sums, updated by adding or
+// removing outer products, and the projections are recomputed from them).
+// mu: host C x D landmarks; KQ: device D x D sum over m_q queries; KX: device
+// C x D x D sums; counts: host C vectors behind each K_{X_c}.
+gv_status fit_from_stats_impl(const double* mu, const double* KQ, double m_q, const double* KX,
+                              const int64_t* counts, hipStream_t st, gv_model* model) {
+  const int C = model->C, D = model->D;
+  const size_t DD = (size_t)D * D;
+  model->KQ.resize(DD);
+  model->KX.resize(DD * C);
+  GV_HIP(hipMemcpyAsync(model->KQ.data(), KQ, sizeof(double) * DD, hipMemcpyDeviceToHost, st));
+  GV_HIP(hipMemcpyAsync(model->KX.data(), KX, sizeof(double) * DD * C, hipMemcpyDeviceToHost, st));
+  GV_HIP(hipMemcpyAsync(model->mu, mu, sizeof(double) * C * D, hipMemcpyHostToDevice, st));
+  GV_HIP(hipStreamSynchronize(st));
+  for (auto& v : model->KQ) v /= m_q;
+  std::vector<int64_t> cnt(counts, counts + C);
+  GV_TRY(sphere_project(model, KX, cnt, model->mu, st));
+  model->iters = 0;
   return GV_OK;
 }
 

@@ -147,15 +147,20 @@ gv_status loss_grad_impl(int C, int d, int D, const float* A, const float* B, co
 
 // K[c] = sum over the rows v of V with tag c of v v^T (FP64 accumulation of
 // exact FP32 products), for c < C; all rows belong to cluster 0 without tags.
-gv_status moments_impl(const float* V, int64_t n, int D, const uint8_t* tags, int C, double* K, hipStream_t st) {
+// sign 0 overwrites K; +1 / -1 adds / subtracts the sums (streaming updates).
+gv_status moments_impl(const float* V, int64_t n, int D, const uint8_t* tags, int C, double* K, hipStream_t st,
+                       int sign) {
   const int64_t DD = (int64_t)D * D;
-  const unsigned fg = (unsigned)std::min<int64_t>(4096, (C * DD + 255) / 256);
-  hipLaunchKernelGGL(k_fill_f64, dim3(fg), dim3(256), 0, st, K, C * DD, 0.0);
-  GV_HIP(hipGetLastError());
+  if (sign == 0) {
+    const unsigned fg = (unsigned)std::min<int64_t>(4096, (C * DD + 255) / 256);
+    hipLaunchKernelGGL(k_fill_f64, dim3(fg), dim3(256), 0, st, K, C * DD, 0.0);
+    GV_HIP(hipGetLastError());
+  }
+  const double alpha = sign < 0 ? -1.0 : 1.0;
   if (n == 0) return GV_OK;
   if (!tags) {
     const GemmOperand<float> v{V, D, nullptr, Layout::KMajor};
-    return gemm_f64<float, float>(D, D, n, v, v, Epi::AddF64, GemmOut{K, D, 0, 0, nullptr}, st);
+    return gemm_f64<float, float>(D, D, n, v, v, Epi::AddF64, GemmOut{K, D, 0, 0, nullptr, 0, alpha}, st);
   }
   // group the rows by tag on the host (statistics are a one-off)
   std::vector<uint8_t> h_tags(n);
@@ -179,7 +184,7 @@ gv_status moments_impl(const float* V, int64_t n, int D, const uint8_t* tags, in
     const int64_t nc = cnt[c + 1] - cnt[c];
     if (nc == 0) continue;
     const GemmOperand<float> v{V, D, d_perm.p + cnt[c], Layout::KMajor};
-    GV_TRY(gemm_f64<float, float>(D, D, nc, v, v, Epi::AddF64, GemmOut{K + DD * c, D, 0, 0, nullptr}, st));
+    GV_TRY(gemm_f64<float, float>(D, D, nc, v, v, Epi::AddF64, GemmOut{K + DD * c, D, 0, 0, nullptr, 0, alpha}, st));
   }
   GV_HIP(hipStreamSynchronize(st));  // the host permutation ends with this call
   return GV_OK;

@@ -648,3 +648,37 @@ def test_euclidean_search_end_to_end():
             assert set(out["ids"][qi].tolist()) == set(order[:5].tolist())
             checked += 1
     assert checked >= 8
+
+
+# ----------------------------------------------------------------------------- streaming updates (Section 3)
+
+def test_streaming_moment_updates_are_exact():
+    """Adding the inserted vectors' outer products and subtracting the removed ones
+    gives the statistics of the final set (integer data: every sum is exact)."""
+    rng = np.random.default_rng(60)
+    X0 = rng.integers(-8, 9, (300, 6)).astype(np.float64)
+    ins = rng.integers(-8, 9, (50, 6)).astype(np.float64)
+    tags0 = rng.integers(0, 3, 300); tags_ins = rng.integers(0, 3, 50)
+    rm = rng.choice(300, 40, replace=False)
+    K0 = np.stack([X0[tags0 == c].T @ X0[tags0 == c] for c in range(3)])
+    K = G.update_moments(K0, ins, tags_ins, +1)
+    K = G.update_moments(K, X0[rm], tags0[rm], -1)
+    keep = np.setdiff1d(np.arange(300), rm)
+    Xf = np.concatenate([X0[keep], ins]); tf = np.concatenate([tags0[keep], tags_ins])
+    want = np.stack([Xf[tf == c].T @ Xf[tf == c] for c in range(3)])
+    assert np.array_equal(K, want)
+
+
+def test_fit_from_stats_equals_fit_with_kept_landmarks():
+    """The projections recomputed from the statistics of a set are those of fitting the
+    set with the landmarks held fixed (no Lloyd step)."""
+    model, X, Q = _small_problem("fp32", seed=61)
+    rng = np.random.default_rng(61)
+    QL = _lowrank_data(rng, 400, X.shape[1]).astype(np.float32)
+    ref = G.fit(X, QL, 5, 4, seed=2, mu0=model.mu, max_iter=0)
+    tags = G.assign(X.astype(np.float64), model.mu)
+    KX = np.stack([G.second_moment(X[tags == c], mean=False) for c in range(4)])
+    KQs = G.second_moment(QL, mean=False)
+    got = G.fit_from_stats(model.mu, KQs, QL.shape[0], KX, np.bincount(tags, minlength=4), 5)
+    assert np.allclose(got.A, ref.A, atol=1e-10) and np.allclose(got.B, ref.B, atol=1e-10)
+    assert np.array_equal(got.fallback, ref.fallback)
