@@ -263,7 +263,7 @@ Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C) {
   } else if (m <= 64) {
     sh.shared = true; sh.nb = 2;
   } else {
-    sh.shared = false; sh.nb = 4;
+    sh.shared = false; sh.nb = 2;  // two wavefronts per SIMD on the LDS ring (see launch_one)
   }
   if (sh.shared && sh.nb > 2) sh.nb = 2;
   if (!sh.shared && sh.nb < 2) sh.nb = 2;

@@ -270,8 +270,9 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   constexpr int kblock_c = 64 * Op::EPL * Op::EB;  // bytes of one k-step block of a tile
   constexpr int TB = KS * kblock_c;                 // bytes of one tile
 
-  // two workgroups per CU, or an LDS tile ring, need the smaller compaction staging
-  constexpr int CAPL = (OCC >= 2 || WGT) ? kCap / 2 : kCap;
+  // two workgroups per CU, or an LDS tile ring, need a smaller compaction staging
+  // (both: a quarter, so that two workgroups fit the LDS)
+  constexpr int CAPL = (OCC >= 2 && WGT) ? kCap / 4 : ((OCC >= 2 || WGT) ? kCap / 2 : kCap);
   static_assert(CAPL - kRows * (U + 1) >= 256 + kRows, "the staging must hold kappa <= 256 plus a tile");
   __shared__ WaveSmem<QW, CAPL> s_wave[4];
   __shared__ __attribute__((aligned(16))) uint8_t s_ring[WGT ? PL * TB : 16];
@@ -695,18 +696,24 @@ struct RingCfg {
   static constexpr int PL = TB <= 10240 ? 5 : 4;
 };
 
+// With two query blocks per wavefront on the LDS ring, two workgroups share a
+// CU (two wavefronts per SIMD, 256 registers each): one wavefront's filter,
+// barrier and LDS waits overlap the other's matrix-core chain.  Its ring is four
+// tiles deep and its compaction staging 512 keys, so two workgroups fit the LDS
+// (tiles up to 12 KiB).
 template <int FMT, int KS, int NB, bool SHARED, int MODE>
 void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   using Cfg = ScanCfg<FMT, KS, NB>;
   constexpr bool W = !SHARED && RingCfg<FMT, KS>::ok;
-  constexpr int PL = W ? RingCfg<FMT, KS>::PL : 1;
+  constexpr int OC = (W && NB == 2) ? 2 : 1;
+  constexpr int PL = W ? (OC == 2 ? 4 : RingCfg<FMT, KS>::PL) : 1;
   constexpr bool DEF = W || Cfg::defer;
   if (MODE == kFilter && args.stride == 1)
-    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, DEF, 1, true, W, PL>), dim3(sh.grid), dim3(256), 0,
+    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, DEF, OC, true, W, PL>), dim3(sh.grid), dim3(256), 0,
                        st, args);
   else
-    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, DEF, 1, false, W, PL>), dim3(sh.grid), dim3(256), 0,
-                       st, args);
+    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, DEF, OC, false, W, PL>), dim3(sh.grid), dim3(256),
+                       0, st, args);
 }
 
 template <int FMT, int KS, int MODE>
