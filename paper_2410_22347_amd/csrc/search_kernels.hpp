@@ -122,8 +122,7 @@ struct WaveSmem {
   float tau[QW];
   uint32_t hist[256];
   uint32_t kept;
-  uint64_t idk[CAPL];  // compaction: keys ordered by (score desc, id asc)
-  uint32_t row[CAPL];  //             and the stored row of each
+  uint64_t idk[CAPL];  // compaction: the list's keys
 };
 
 // Reduce the list L of n keys (n > keep), keyed (score desc, stored row asc),
@@ -169,20 +168,18 @@ __device__ int compact_list(uint64_t* L, int n, int keep, int room, const int32_
     wave_sync();
     return c;
   }
-  // many ties at the keep-th best score: exact reduction by original id
-  for (int i = lane; i < n; i += 64) {
-    const uint64_t k = w.idk[i];
+  // many ties at the keep-th best score: exact reduction by original id (the
+  // id of each key is looked up where it is compared; this path is rare)
+  auto by_id = [&](uint64_t k) {
     const uint32_t row = 0xFFFFFFFFu - (uint32_t)k;
-    w.idk[i] = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - (uint32_t)ids[row]);
-    w.row[i] = row;
-  }
-  wave_sync();
-  const uint64_t kid = wave_kth([&](int i) { return w.idk[i]; }, n, keep, w.hist);
+    return (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - (uint32_t)ids[row]);
+  };
+  const uint64_t kid = wave_kth([&](int i) { return by_id(w.idk[i]); }, n, keep, w.hist);
   if (lane == 0) w.kept = 0;
   wave_sync();
   for (int i = lane; i < n; i += 64) {
     const uint64_t k = w.idk[i];
-    if (k >= kid) L[atomicAdd(&w.kept, 1u)] = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - w.row[i]);
+    if (by_id(k) >= kid) L[atomicAdd(&w.kept, 1u)] = k;
   }
   wave_sync();
   return keep;
@@ -270,9 +267,8 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   constexpr int kblock_c = 64 * Op::EPL * Op::EB;  // bytes of one k-step block of a tile
   constexpr int TB = KS * kblock_c;                 // bytes of one tile
 
-  // two workgroups per CU, or an LDS tile ring, need a smaller compaction staging
-  // (both: a quarter, so that two workgroups fit the LDS)
-  constexpr int CAPL = (OCC >= 2 && WGT) ? kCap / 4 : ((OCC >= 2 || WGT) ? kCap / 2 : kCap);
+  // two workgroups per CU, or an LDS tile ring, need the smaller compaction staging
+  constexpr int CAPL = (OCC >= 2 || WGT) ? kCap / 2 : kCap;
   static_assert(CAPL - kRows * (U + 1) >= 256 + kRows, "the staging must hold kappa <= 256 plus a tile");
   __shared__ WaveSmem<QW, CAPL> s_wave[4];
   __shared__ __attribute__((aligned(16))) uint8_t s_ring[WGT ? PL * TB : 16];
@@ -699,8 +695,8 @@ struct RingCfg {
 // With two query blocks per wavefront on the LDS ring, two workgroups share a
 // CU (two wavefronts per SIMD, 256 registers each): one wavefront's filter,
 // barrier and LDS waits overlap the other's matrix-core chain.  Its ring is four
-// tiles deep and its compaction staging 512 keys, so two workgroups fit the LDS
-// (tiles up to 12 KiB).
+// tiles deep and its compaction staging 1024 keys, so two workgroups fit the LDS
+// (tiles up to 10 KiB).
 template <int FMT, int KS, int NB, bool SHARED, int MODE>
 void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   using Cfg = ScanCfg<FMT, KS, NB>;
