@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1_000_000)
-    ap.add_argument("--cpu-queries", type=int, default=32)
+    ap.add_argument("--cpu-queries", type=int, default=128)
     ap.add_argument("--splits", type=int, default=0, help="override the row ranges per query block (0: automatic)")
     ap.add_argument("--qpw", type=int, default=0, help="override the queries per wavefront (0: automatic)")
     ap.add_argument("--batched", action="store_true",
