@@ -10,8 +10,9 @@
 //
 // Tiling: a 256-thread workgroup owns a 64 x 64 output tile; its four
 // wavefronts each own 32 x 32 (2 x 2 blocks of 16 x 16).  K advances in steps
-// of 16 through LDS, stored k-major so every MFMA operand read is a
-// contiguous 16-element row.
+// of 32 through LDS, stored k-major so every MFMA operand read is a
+// contiguous 16-element row.  The next step's operands are loaded into
+// registers while the matrix core works on the current one.
 #include "common.hpp"
 
 namespace gv {
@@ -19,37 +20,51 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 64, TN = 64, TK = 16, LDSP = TM + 2;
+constexpr int TM = 64, TN = 64, TK = 32, LDSP = TM + 2;
+constexpr int SE = TK * TM / 256;  // slab elements per thread
 
 template <typename T>
 __device__ inline double ld_elem(const T* p, int64_t idx) {
   return (double)p[idx];
 }
 
-// Stage a TK x 64 slab of an operand into LDS (k-major: s[k][i]).
+// A TK x 64 slab of an operand into registers (RowMajor: thread -> row i0 +
+// tid / 4, k0 + SE * (tid % 4) ..; KMajor: thread -> k0 + tid / 8, i0 + SE *
+// (tid % 8) ..), zero outside the operand.
 template <typename T>
-__device__ inline void stage(double (*s)[LDSP], GemmOperand<T> op, int64_t i0, int64_t k0,
-                             int64_t M, int64_t K, int tid) {
+__device__ inline void load_slab(double (&r)[SE], GemmOperand<T> op, int64_t i0, int64_t k0, int64_t M, int64_t K,
+                                 int tid) {
   if (op.layout == Layout::RowMajor) {
-    // thread -> (row i0 + tid/4, k0 + 4*(tid%4) .. +3)
-    int r = tid >> 2, kq = (tid & 3) * 4;
-    int64_t i = i0 + r;
-    int64_t row = (i < M) ? (op.gather ? op.gather[i] : i) : 0;
+    const int rr = tid >> 2, kq = (tid & 3) * SE;
+    const int64_t i = i0 + rr;
+    const int64_t row = (i < M) ? (op.gather ? op.gather[i] : i) : 0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int64_t k = k0 + kq + e;
-      s[kq + e][r] = (i < M && k < K) ? ld_elem(op.p, row * op.ld + k) : 0.0;
+    for (int e = 0; e < SE; ++e) {
+      const int64_t k = k0 + kq + e;
+      r[e] = (i < M && k < K) ? ld_elem(op.p, row * op.ld + k) : 0.0;
     }
   } else {
-    // thread -> (k0 + tid/16, i0 + 4*(tid%16) .. +3)
-    int kr = tid >> 4, iq = (tid & 15) * 4;
-    int64_t k = k0 + kr;
-    int64_t row = (k < K) ? (op.gather ? op.gather[k] : k) : 0;
+    const int kr = tid >> 3, iq = (tid & 7) * SE;
+    const int64_t k = k0 + kr;
+    const int64_t row = (k < K) ? (op.gather ? op.gather[k] : k) : 0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int64_t i = i0 + iq + e;
-      s[kr][iq + e] = (i < M && k < K) ? ld_elem(op.p, row * op.ld + i) : 0.0;
+    for (int e = 0; e < SE; ++e) {
+      const int64_t i = i0 + iq + e;
+      r[e] = (i < M && k < K) ? ld_elem(op.p, row * op.ld + i) : 0.0;
     }
+  }
+}
+
+// the registers of load_slab into the k-major LDS slab s[k][i]
+__device__ inline void store_slab(double (*s)[LDSP], const double (&r)[SE], Layout layout, int tid) {
+  if (layout == Layout::RowMajor) {
+    const int rr = tid >> 2, kq = (tid & 3) * SE;
+#pragma unroll
+    for (int e = 0; e < SE; ++e) s[kq + e][rr] = r[e];
+  } else {
+    const int kr = tid >> 3, iq = (tid & 7) * SE;
+#pragma unroll
+    for (int e = 0; e < SE; ++e) s[kr][iq + e] = r[e];
   }
 }
 
@@ -72,10 +87,17 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int64_t M, int64_t N, int64_t 
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
 
+  double ra[SE], rb[SE];
+  load_slab(ra, a, i0, 0, M, K, tid);
+  load_slab(rb, b, j0, 0, N, K, tid);
   for (int64_t k0 = 0; k0 < K; k0 += TK) {
-    stage(As, a, i0, k0, M, K, tid);
-    stage(Bs, b, j0, k0, N, K, tid);
+    store_slab(As, ra, a.layout, tid);
+    store_slab(Bs, rb, b.layout, tid);
     __syncthreads();
+    if (k0 + TK < K) {  // the next step's operands travel while this one is multiplied
+      load_slab(ra, a, i0, k0 + TK, M, K, tid);
+      load_slab(rb, b, j0, k0 + TK, N, K, tid);
+    }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4), c = lane & 15;
