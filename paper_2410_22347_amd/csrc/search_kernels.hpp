@@ -531,8 +531,10 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
       // (asm copies: the compiler does not order LDS reads behind them); after
       // its own copies of a tile land (memory counter) and a barrier, every
       // wavefront may read the whole tile.  Vector memory operations complete
-      // in order, so a wait counts the copies issued after the tile's, whatever
-      // stores happen in between.  The reads of tile t + 1 go out before the
+      // in order, so "at most N outstanding", N = the copies issued after the
+      // tile's, is met only once the tile's copies have landed.  Survivor
+      // stores issued in between count too: the wait is then longer than
+      // needed, never shorter.  The reads of tile t + 1 go out before the
       // matrix-core chain of tile t and land while it runs.
       static_assert(TB % 1024 == 0, "tiles are copied in 1 KiB chunks");
       constexpr int NCH = TB / 1024;
