@@ -25,7 +25,7 @@ Readings of points the paper leaves open (also listed in the design notes):
 * storage formats and scales (not in the paper): per-cluster power-of-two
   scale s_c for the database and per-(query, cluster) scale t for the query
   view, both mapping the block's amax into (T/2, T], then round-to-nearest-even
-  (see ``formats``).
+  (see ``formats``); FP8 storage meets FP16 query views (``VIEW_FORMAT``).
 """
 from __future__ import annotations
 
@@ -317,18 +317,27 @@ def encode(model_mu: np.ndarray, B: np.ndarray, X: np.ndarray, fmt: str) -> Inde
 
 
 # ============================================================================ search
+# Format of the query view q^ that meets the stored vectors in the reduced inner
+# product (not in the paper): the storage format itself, except FP8 storage,
+# whose scores are formed with FP16 query views -- FP16 x E4M3 products are
+# exact, so FP8 storage halves the bytes read without rounding the query to
+# three fraction bits.
+VIEW_FORMAT = {"fp32": "fp32", "fp16": "fp16", "bf16": "bf16", "fp8": "fp16"}
+
+
 def project_queries(A: np.ndarray, Q: np.ndarray, fmt: str):
     """Eager preprocessing (Algorithm 4, preprocess): q_c = A_c q for every c in
-    float64, rounded once to FP32; then the per-
-    (query, cluster) power-of-two scale t and the stored-format view q^ = rnd(q_c / t).
+    float64, rounded once to FP32; then the per-(query, cluster) power-of-two
+    scale t and the view q^ = rnd(q_c / t) in VIEW_FORMAT[fmt].
     Returns (q_c [m, C, d], t [m, C], q^ [m, C, d])."""
     A64 = np.asarray(A, np.float64)
     Q64 = np.asarray(Q, np.float64)
     C, d, D = A64.shape
     qc = formats.round_to("fp32", (Q64 @ A64.reshape(C * d, D).T).reshape(-1, C, d))
     amax = np.max(np.abs(qc), axis=2)
-    t = formats.pow2_scale(fmt, amax)
-    qh = formats.round_to(fmt, qc / t[:, :, None])
+    vf = VIEW_FORMAT[fmt]
+    t = formats.pow2_scale(vf, amax)
+    qh = formats.round_to(vf, qc / t[:, :, None])
     return qc, t, qh
 
 
@@ -398,7 +407,7 @@ def augment_queries(Q: np.ndarray) -> np.ndarray:
 def project_queries_flex(A: np.ndarray, Q: np.ndarray, fmt: str, d_search: int):
     """Eager views on the leading d_search coordinates: q_c = fl32(A_c q) over all
     d_s stored rows (the rerank from stored vectors uses them all); the scale t and
-    the storage-format view q^ come from the first d_search values only.
+    the view q^ (in VIEW_FORMAT[fmt]) come from the first d_search values only.
     Returns (q_c [m, C, d_s], t [m, C], q^ [m, C, d_search])."""
     A64 = np.asarray(A, np.float64)
     Q64 = np.asarray(Q, np.float64)
@@ -406,8 +415,9 @@ def project_queries_flex(A: np.ndarray, Q: np.ndarray, fmt: str, d_search: int):
     assert 1 <= d_search <= d
     qc = formats.round_to("fp32", (Q64 @ A64.reshape(C * d, D).T).reshape(-1, C, d))
     lead = qc[:, :, :d_search]
-    t = formats.pow2_scale(fmt, np.max(np.abs(lead), axis=2))
-    qh = formats.round_to(fmt, lead / t[:, :, None])
+    vf = VIEW_FORMAT[fmt]
+    t = formats.pow2_scale(vf, np.max(np.abs(lead), axis=2))
+    qh = formats.round_to(vf, lead / t[:, :, None])
     return qc, t, qh
 
 

@@ -43,9 +43,19 @@ def sources():
     return hip, cpp
 
 
-def compile_one(src: str) -> str:
+def _newest_dependency() -> float:
+    """Latest modification time among the headers every source may include."""
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    heads.append(os.path.join(ROOT, "include", "gleanvec.h"))
+    return max(os.path.getmtime(h) for h in heads)
+
+
+def compile_one(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, src + ".o")
     path = os.path.join(CSRC, src)
+    if incremental and os.path.exists(obj):
+        if os.path.getmtime(obj) >= max(os.path.getmtime(path), _newest_dependency()):
+            return obj
     if src.endswith(".hip"):
         cmd = [hipcc(), *HIP_FLAGS, "-c", path, "-o", obj]
     else:
@@ -56,12 +66,16 @@ def compile_one(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those older than their object
+    or than a header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     hip, cpp = sources()
     jobs = jobs or min(8, os.cpu_count() or 4)
+    # the scan instantiations are the slowest units: start them first
+    order = sorted(hip, key=lambda f: not f.startswith("scan_")) + cpp
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_one, hip + cpp))
+        objs = list(ex.map(lambda f: compile_one(f, incremental), order))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -76,8 +90,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true", help="recompile only sources changed since their object")
     a = ap.parse_args()
-    build(a.jobs, verbose=True)
+    build(a.jobs, verbose=True, incremental=a.incremental)
 
 
 if __name__ == "__main__":

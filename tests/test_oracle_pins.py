@@ -225,6 +225,64 @@ def test_kmeanspp_draws_far_points():
         assert np.unique(np.round(mu, 12), axis=0).shape[0] == 5
 
 
+class _ScriptedDraws:
+    """Stands in for the generator: returns the given integers and uniforms in order."""
+
+    def __init__(self, ints, uniforms):
+        self.ints = list(ints)
+        self.uniforms = list(uniforms)
+
+    def next(self):
+        return self.ints.pop(0)
+
+    def uniform(self):
+        return self.uniforms.pop(0)
+
+
+# Three unit points worked by hand: with the first centre at x0 = (1, 0), the
+# squared chord distances 2 - 2 <x, x0> are 0, 2, 4 for x0, x1 = (0, 1),
+# x2 = (-1, 0); their prefix sums are 0, 2, 6 of a total 6.  The D^2 law of
+# k-means++ picks x1 with probability 2/6 and x2 with 4/6 (a law on the plain
+# distance would give sqrt(2) / (sqrt(2) + 2) = 0.414 for x1).
+_KPP_POINTS = np.array([[1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])
+
+
+def test_kmeanspp_draw_follows_squared_distance_law():
+    # exact picks for given uniforms: the first index whose prefix sum exceeds u * total
+    for u, want in [(0.0, 1), (0.30, 1), (0.3333, 1), (0.334, 2), (0.9, 2)]:
+        mu = G.kmeanspp(_KPP_POINTS, 2, _ScriptedDraws([0], [u]))
+        assert np.array_equal(mu[1], _KPP_POINTS[want]), (u, want)
+    # frequencies over SplitMix64 seeds whose first centre is x0
+    picks = []
+    seed = 0
+    while len(picks) < 3000:
+        gen = SplitMix64(seed)
+        seed += 1
+        probe = SplitMix64(gen.state)
+        if probe.next() % 3 != 0:
+            continue
+        mu = G.kmeanspp(_KPP_POINTS, 2, gen)
+        picks.append(int(np.argmax(_KPP_POINTS @ mu[1])))
+    f1 = np.mean(np.array(picks) == 1)
+    assert abs(f1 - 1.0 / 3.0) < 0.03, f1       # D^2 law: 1/3 (sd 0.009)
+    assert abs(f1 - 0.414) > 0.05               # the plain-distance law is ruled out
+
+
+def test_kmeanspp_tie_at_the_boundary_takes_the_next_point():
+    """A uniform that lands exactly on a prefix sum: with x0 = (1, 0) first,
+    x1 = (0, 1) and x2 = (0, -1) are both at squared chord distance 2; the prefix
+    sums are 0, 2, 4 and u = 1/2 gives u * total = 2 exactly.  The draw takes the
+    first index whose prefix sum strictly exceeds it, x2."""
+    P = np.array([[1.0, 0.0], [0.0, 1.0], [0.0, -1.0]])
+    mu = G.kmeanspp(P, 2, _ScriptedDraws([0], [0.5]))
+    assert np.array_equal(mu[1], P[2])
+    mu = G.kmeanspp(P, 2, _ScriptedDraws([0], [0.4999999]))
+    assert np.array_equal(mu[1], P[1])
+    # the third centre of three: distances to the nearest of {x0, x2} are 0, 2, 0
+    mu = G.kmeanspp(P, 3, _ScriptedDraws([0], [0.5, 0.99]))
+    assert np.array_equal(mu[2], P[1])
+
+
 # ----------------------------------------------------------------------------- sphering (T1-T10, T14-T16)
 
 def _fitdata(seed, n=600, m=400, D=12):
@@ -483,6 +541,40 @@ def test_encode_definition(fmt):
         assert np.allclose(idx.v[p], exact, rtol=2 ** -23, atol=0)
         s = idx.scale[c]
         assert np.all(np.abs(idx.xq[p] * s - idx.v[p]) <= np.abs(idx.v[p]) * (2 ** -3 if fmt == "fp8" else 2 ** -7) + s * 2 ** -6)
+    # the per-cluster scale from its definition: a power of two putting the cluster's
+    # largest |v| into (T/2, T] (T = 448, 65504, 1; FP32 unscaled)
+    T = {"fp32": None, "fp16": 65504.0, "bf16": 1.0, "fp8": 448.0}[fmt]
+    for c in range(model.C):
+        a, b = idx.offsets[c], idx.offsets[c + 1]
+        s = idx.scale[c]
+        if T is None or a == b:
+            assert s == 1.0
+            continue
+        amax = np.abs(idx.v[a:b]).max()
+        mant, _ = math.frexp(s)
+        assert mant == 0.5, s                       # a power of two
+        assert T / 2 < amax / s <= T, (c, amax, s)
+        assert np.abs(idx.xq[a:b]).max() <= T        # no saturation was needed
+    # every stored value is the nearest value of the format to v / s (ties to even),
+    # checked against the format's grid written out from its definition
+    M, emin = {"fp32": (23, -126), "fp16": (10, -14), "bf16": (7, -126), "fp8": (3, -6)}[fmt]
+    for c in range(model.C):
+        a, b = idx.offsets[c], idx.offsets[c + 1]
+        y = (idx.v[a:b] / idx.scale[c]).ravel()
+        got = idx.xq[a:b].ravel()
+        e = np.array([max(math.frexp(abs(v))[1] - 1, emin) if v != 0 else emin for v in y])
+        q = np.ldexp(1.0, e - M)                  # spacing of the grid around each value
+        lo = np.floor(y / q) * q
+        hi = lo + q
+        dlo, dhi = y - lo, hi - y
+        want = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi,
+                        np.where(np.mod(np.round(lo / q), 2) == 0, lo, hi)))
+        assert np.array_equal(got, want), fmt
+    if fmt == "fp16":   # a second opinion: numpy's own binary16 conversion
+        for c in range(model.C):
+            a, b = idx.offsets[c], idx.offsets[c + 1]
+            y = idx.v[a:b] / idx.scale[c]
+            assert np.array_equal(idx.xq[a:b], y.astype(np.float16).astype(np.float64))
 
 
 @pytest.mark.parametrize("fmt", ["fp32", "fp16", "bf16", "fp8"])
@@ -508,6 +600,34 @@ def test_search_stages_against_brute_force(fmt):
     # the FP32 view approximates the exact A_c q
     qc_exact = np.einsum("cjD,mD->mcj", model.A, Q.astype(np.float64))
     assert np.allclose(out["qc"], qc_exact, rtol=2 ** -23, atol=0)
+
+
+@pytest.mark.parametrize("fmt", ["fp32", "fp16", "bf16", "fp8"])
+def test_query_view_definition(fmt):
+    """The query view: t a power of two putting max_j |q_c,j| into (T/2, T] of the
+    view format, q^ the nearest value of that format to q_c / t.  FP8 storage meets
+    FP16 views, checked against numpy's own binary16 rounding; FP32 is unscaled."""
+    model, X, Q = _small_problem(fmt, seed=23)
+    qc, t, qh = G.project_queries(model.A, Q, fmt)
+    exact = np.einsum("cjD,mD->mcj", model.A, Q.astype(np.float64))
+    assert np.array_equal(qc, exact.astype(np.float32).astype(np.float64))
+    if fmt == "fp32":
+        assert np.all(t == 1.0) and np.array_equal(qh, qc)
+        return
+    T = {"fp16": 65504.0, "bf16": 1.0, "fp8": 65504.0}[fmt]
+    amax = np.abs(qc).max(axis=2)
+    assert np.all((T / 2 < amax / t) & (amax / t <= T))
+    assert np.all(np.frexp(t)[0] == 0.5)
+    y = qc / t[:, :, None]
+    if fmt in ("fp16", "fp8"):
+        assert np.array_equal(qh, y.astype(np.float16).astype(np.float64))
+    else:  # bf16: nearest of the 8-bit-significand grid, ties to even
+        e = np.maximum(np.frexp(np.abs(y))[1] - 1, -126)
+        q = np.ldexp(1.0, e - 7)
+        lo = np.floor(y / q) * q
+        want = np.where(y - lo < lo + q - y, lo, np.where(y - lo > lo + q - y, lo + q,
+                        np.where(np.mod(np.round(lo / q), 2) == 0, lo, lo + q)))
+        assert np.array_equal(qh, want)
 
 
 def test_search_full_dimension_recovers_exact_topk():
@@ -585,7 +705,8 @@ def test_flex_stages_against_brute_force(fmt):
     assert np.allclose(out["qc"], qc_exact, rtol=2 ** -23, atol=0) and out["qc"].shape[2] == model.d
     for qi in range(Q.shape[0]):
         amax = np.abs(out["qc"][qi, :, :ds]).max(axis=1)
-        assert np.array_equal(out["t"][qi], formats.pow2_scale(fmt, amax))
+        # the scale of the leading d_search values (FP8 storage: FP16 views, T = 65504)
+        assert np.array_equal(out["t"][qi], formats.pow2_scale("fp16" if fmt == "fp8" else fmt, amax))
         s = np.empty(n)
         for i in range(n):
             c = idx.tags[i]
