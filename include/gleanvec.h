@@ -51,7 +51,8 @@ typedef enum {
   GV_EDEVICE = -3,       /* a HIP runtime call failed */
   GV_ENOTFIT = -4,       /* the handle is NULL or was not produced by this library */
   GV_ENONFINITE = -5,    /* an input holds NaN or +-Inf */
-  GV_EUNSUPPORTED = -6   /* valid request that this build does not handle */
+  GV_EUNSUPPORTED = -6,  /* valid request that this build does not handle */
+  GV_ENOCONV = -7        /* an eigendecomposition of the fit did not converge */
 } gv_status;
 
 /* Storage format of the reduced vectors (and of the query views they meet). */
@@ -133,10 +134,50 @@ gv_status gv_model_export(const gv_model* model, double* mu, double* A, double* 
  * per-cluster sums), lam_Q (D, eigenvalues of K_Q, decreasing), lam_c
  * (C x D, eigenvalues of W K_{X_c} W, decreasing), counts (C learn vectors
  * per cluster), fallback (C flags: pooled projection used), iters (k-means
- * centre updates).  Imported models return GV_EUNSUPPORTED.
+ * centre updates).  Imported models (and loaded files without statistics)
+ * return GV_EUNSUPPORTED.
  */
 gv_status gv_model_stats(const gv_model* model, double* KQ, double* KX, double* lam_Q,
                          double* lam_c, int64_t* counts, uint8_t* fallback, int32_t* iters);
+
+/*
+ * gv_model_sphering -- the sphering factors of a fitted model (Section 3: W
+ * with W W = K_Q, its pseudo-inverse W+) and the per-cluster projections P_c
+ * with A_c = P_c W+, B_c = P_c W (Algorithm 2 through the eigendecompositions
+ * of Section 3.2).  Host FP64 arrays, any may be NULL: W, Wp D x D; P C x d x D.
+ * Imported models return GV_EUNSUPPORTED.
+ */
+gv_status gv_model_sphering(const gv_model* model, double* W, double* Wp, double* P);
+
+/*
+ * gv_model_save / gv_model_load -- the model as one file: landmarks mu, the
+ * projections A_c and B_c and, for fitted models, the FP64 statistics K_Q
+ * (mean) and K_{X_c} (sums), the eigenvalues, W, W+, P_c, the per-cluster
+ * counts and fallback flags and the k-means step count -- everything from
+ * which Section 3.2 recomputes the projections (for instance after streaming
+ * updates of the statistics).  Loading restores every value bit for bit into a
+ * new handle on the current device, so a search with it returns what the saved
+ * model's returns; gv_model_stats and gv_model_sphering work on it when the
+ * file holds statistics.  The file is little-endian binary:
+ *   "GLEANVEC", u32 version (1), u32 flags (bit 0: statistics), i32 C, d, D,
+ *   iters; f64 mu[C*D], A[C*d*D], B[C*d*D]; with statistics f64 KQ[D*D],
+ *   KX[C*D*D], lam_Q[D], lam_c[C*D], W[D*D], W+[D*D], P[C*d*D], i64 counts[C],
+ *   u8 fallback[C]; then the 64-bit FNV-1a of every preceding byte.
+ * path: host NUL-terminated file name (overwritten by gv_model_save).
+ * Errors: GV_ENOTFIT, GV_EINVAL (NULL path, unreadable or corrupt file: bad
+ * magic, header, size or checksum), GV_EUNSUPPORTED (other file version),
+ * GV_ENOMEM, GV_EDEVICE (device copies, write failure).
+ */
+gv_status gv_model_save(const gv_model* model, const char* path);
+gv_status gv_model_load(const char* path, gv_model** out);
+
+/*
+ * gv_model_file_info -- validate a model file (magic, version, shape, size,
+ * checksum) without touching the device, and return its shape (any pointer
+ * may be NULL; has_stats: 1 if it holds the statistics).  Errors as
+ * gv_model_load's file checks.
+ */
+gv_status gv_model_file_info(const char* path, int32_t* C, int32_t* d, int32_t* D, int32_t* has_stats);
 
 void gv_model_destroy(gv_model* model);
 
@@ -191,7 +232,8 @@ void gv_index_destroy(gv_index* index);
  * gv_search -- multi-step search (Algorithm 1) with eager views (Algorithm 4).
  *
  * Q           device, m x D FP32 queries (m >= 0; m == 0 is a no-op).
- * k, kappa    1 <= k <= kappa <= min(n, 256).
+ * k, kappa    1 <= k <= kappa <= min(n, 1024); kappa above a launch shape's
+ *             candidate lists (see gv_scan_plan) returns GV_EUNSUPPORTED.
  * out_ids     device, m x k int32: original row ids of the k best rerank
  *             scores, ordered by (exact score desc, id asc).
  * out_scores  device, m x k FP32 (may be NULL): fl32 of the exact <q, x>
@@ -200,7 +242,8 @@ void gv_index_destroy(gv_index* index);
  * Stages, one launch sequence on `stream`:
  *   S1  q_c = fl32(A_c q) for every cluster (FP64 accumulation), then the
  *       per-(query, cluster) power-of-two scale t and the view
- *       q^_c = rnd(q_c / t) in the index format (t = 1 for FP32);
+ *       q^_c = rnd(q_c / t) in the view format of the index: its storage
+ *       format, FP16 for FP8 storage (t = 1 for FP32);
  *   S2  for every database vector i of cluster c:
  *       s_i = s_c * t_{q,c} * <q^_c, x^_i>, FP32 accumulation on the matrix cores;
  *   S3  the kappa best s_i per query, ordered by (s_i desc, id asc);
@@ -237,11 +280,19 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
 /* gv_batch_release -- free the graph and workspace kept by gv_search_batched. */
 void gv_batch_release(void);
 
+/* gv_batch_counts -- how many gv_search_batched calls since the library was
+ * loaded captured a new graph and how many replayed the kept one (either
+ * pointer may be NULL).  A handle enters the replay key by a generation number
+ * unique to it, so a model or index destroyed and another created at the same
+ * address leads to a new capture. */
+void gv_batch_counts(int64_t* captures, int64_t* replays);
+
 /*
  * gv_project -- stage S1 alone (Algorithm 4, preprocess).
  * Q device m x D FP32.  qc device m x C x d_pad FP32 (may be NULL): q_c,
  * zero padded, d_pad = gv_padded_dim(d).  t device m x C FP32: the scales.  qhat device m x C x d_pad
- * elements of `fmt` (raw bits, zero padded).  Errors as gv_search.
+ * elements of the view format of `fmt` -- `fmt` itself, FP16 (2 bytes) for
+ * GV_FP8_E4M3 -- (raw bits, zero padded).  Errors as gv_search.
  */
 gv_status gv_project(const gv_model* model, gv_format fmt, const float* Q, int64_t m,
                      float* qc, float* t, void* qhat, void* stream);
@@ -251,7 +302,7 @@ gv_status gv_project(const gv_model* model, gv_format fmt, const float* Q, int64
  * qhat, t  device, as written by gv_project for this index's format.
  * cand_ids device m x kappa int32, cand_scores device m x kappa FP32:
  * the kappa best reduced scores per query, ordered by (score desc, id asc);
- * ids are original row ids.  1 <= kappa <= min(n, 256).  Errors as gv_search.
+ * ids are original row ids.  1 <= kappa <= min(n, 1024).  Errors as gv_search.
  */
 gv_status gv_score_topk(const gv_index* index, const void* qhat, const float* t, int64_t m,
                         int32_t kappa, int32_t* cand_ids, float* cand_scores, void* stream);
@@ -261,7 +312,7 @@ gv_status gv_score_topk(const gv_index* index, const void* qhat, const float* t,
  * Q device m x D FP32; cand_ids device m x kappa int32 (valid original ids);
  * out_ids device m x k int32, out_scores device m x k FP32 (may be NULL):
  * the k best exact <q, x> (FP64 accumulation) among the candidates, ordered by
- * (score desc, id asc).  1 <= k <= kappa <= 256.  Errors as gv_search.
+ * (score desc, id asc).  1 <= k <= kappa <= 1024.  Errors as gv_search.
  */
 gv_status gv_rerank(const gv_index* index, const float* Q, int64_t m, const int32_t* cand_ids,
                     int32_t kappa, int32_t k, int32_t* out_ids, float* out_scores, void* stream);
@@ -326,7 +377,8 @@ gv_status gv_search_flex(const gv_model* model, const gv_index* index, const flo
  * gv_project_flex -- stage S1 of gv_search_flex.  qc device m x C x d_pad FP32
  * (d_pad = gv_padded_dim(d); may be NULL): q_c over all d rows, zero padded.
  * t device m x C FP32: scales of the first d_search values.  qhat device
- * m x C x gv_padded_dim(d_search) elements of `fmt`: the views of the first
+ * m x C x gv_padded_dim(d_search) elements of the view format of `fmt` (FP16
+ * for GV_FP8_E4M3, else `fmt`): the views of the first
  * d_search values, zero padded.  Errors as gv_search_flex.
  */
 gv_status gv_project_flex(const gv_model* model, gv_format fmt, const float* Q, int64_t m,
@@ -364,6 +416,42 @@ gv_status gv_rerank_stored(const gv_index* index, const float* qc, int64_t m, co
  * do not depend on these; only speed does.  Errors: GV_EINVAL.
  */
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap);
+
+/* One level of the S2/S3 launch plan (gv_scan_plan). */
+typedef struct {
+  int64_t stride;            /* the level scans every stride-th 32-row tile (1: the whole database) */
+  int64_t rows_per_level;    /* stored rows the level visits */
+  int64_t query_blocks;      /* blocks of queries_per_wave queries */
+  int32_t dense;             /* 1: dense sample (every score written), 0: filtered candidate lists */
+  int32_t ranges;            /* R: row ranges per query block (one candidate list each) */
+  int32_t grid;              /* workgroups of 256 threads */
+  int32_t queries_per_wave;  /* 32, 64 or 128 */
+  int32_t shared;            /* 1: one query block on four ranges per workgroup */
+  int32_t xcd_map;           /* 1: workgroups sharing rows pinned to one XCD */
+  int32_t tile_ring;         /* 1: tiles shared by the workgroup through an LDS ring */
+  int32_t workgroups_per_cu; /* occupancy the kernel is built for */
+  int32_t check_every;       /* U: tiles between two overflow checks of a list */
+  int32_t staging;           /* keys a compaction stages in the wavefront's LDS */
+  int32_t list_cap;          /* key slots per (query, range) list */
+  int32_t list_limit;        /* a list holding more keys is compacted to its kappa best */
+} gv_scan_level;
+
+/*
+ * gv_scan_plan -- the launch plan of stages S2 and S3 for an index of n rows
+ * stored as n_pad (every cluster segment padded to whole 32-row tiles, so
+ * n <= n_pad <= n + 31 C, a multiple of 32), C clusters, format fmt, reduced
+ * dimension d, a scan of the leading d_search coordinates (0: all of d), m
+ * queries and kappa candidates, under the calling thread's gv_search_tuning.
+ * Host only: computes what gv_score_topk would launch, without a device.
+ * levels (host, max_levels entries, may be NULL) receives the cascade levels,
+ * sparsest first; n_levels their count; list_keys the candidate-list slots of
+ * the scratch (m x max ranges x list_cap); scratch_bytes the scan's scratch.
+ * Errors: GV_EINVAL (sizes), GV_EUNSUPPORTED (a plan gv_score_topk would
+ * refuse: too many list slots for the batch, kappa beyond a shape's lists).
+ */
+gv_status gv_scan_plan(int64_t n, int64_t n_pad, int32_t C, gv_format fmt, int32_t d, int32_t d_search, int64_t m,
+                       int32_t kappa, gv_scan_level* levels, int32_t max_levels, int32_t* n_levels,
+                       int64_t* list_keys, int64_t* scratch_bytes);
 
 /*
  * gv_padded_dim -- the padded row length d_pad used for a reduced dimension d:
@@ -463,9 +551,19 @@ gv_status gv_loss_grad(int32_t C, int32_t d, int32_t D, const float* A, const fl
  * eigendecompositions of Section 3.2 (Householder tridiagonalisation, then
  * implicit QR steps with Wilkinson shifts).  A: host n x n symmetric, read
  * only; lam: host n eigenvalues, decreasing; Vt: host n x n, row r is the unit
- * eigenvector of lam[r].  Runs on the CPU only.  Errors: GV_EINVAL.
+ * eigenvector of lam[r].  Runs on the CPU only.  Errors: GV_EINVAL, GV_ENOCONV.
  */
 gv_status gv_host_eigh(int32_t n, const double* A, double* lam, double* Vt);
+
+/*
+ * gv_eig_step_limit -- the budget of implicit QR steps of one decomposition by
+ * the host eigensolver (0, the default: 60 times the matrix order).  When a
+ * decomposition needs more, gv_host_eigh, gv_fit and gv_fit_from_stats return
+ * GV_ENOCONV instead of projections from an unconverged solve.  Process-wide.
+ * Small budgets exist to exercise that error path.  Errors: GV_EINVAL
+ * (negative budget).
+ */
+gv_status gv_eig_step_limit(int32_t max_steps);
 
 #ifdef __cplusplus
 }

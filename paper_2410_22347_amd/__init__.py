@@ -21,7 +21,7 @@ FORMATS = {"fp32": FP32, "fp16": FP16, "bf16": BF16, "fp8": FP8}
 FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
 
 _STATUS = {0: "GV_OK", -1: "GV_EINVAL", -2: "GV_ENOMEM", -3: "GV_EDEVICE", -4: "GV_ENOTFIT",
-           -5: "GV_ENONFINITE", -6: "GV_EUNSUPPORTED"}
+           -5: "GV_ENONFINITE", -6: "GV_EUNSUPPORTED", -7: "GV_ENOCONV"}
 
 EXPORTED = [
     "gv_status_string", "gv_last_error", "gv_fit", "gv_model_import", "gv_model_shape",
@@ -30,7 +30,8 @@ EXPORTED = [
     "gv_rerank", "gv_search_tuning", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
     "gv_padded_dim", "gv_tags", "gv_moments", "gv_loss_grad", "gv_search_batched", "gv_batch_release",
     "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored", "gv_augment",
-    "gv_moments_update", "gv_fit_from_stats",
+    "gv_moments_update", "gv_fit_from_stats", "gv_batch_counts", "gv_eig_step_limit",
+    "gv_model_save", "gv_model_load", "gv_model_file_info", "gv_model_sphering", "gv_scan_plan",
 ]
 
 
@@ -89,10 +90,19 @@ _sig("gv_score_topk_flex", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_rerank_stored", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_padded_dim", [_i32], _i32)
 _sig("gv_host_eigh", [_i32, _vp, _vp, _vp])
+_sig("gv_eig_step_limit", [_i32])
+_sig("gv_model_save", [_vp, ctypes.c_char_p])
+_sig("gv_model_load", [ctypes.c_char_p, ctypes.POINTER(_vp)])
+_sig("gv_model_file_info", [ctypes.c_char_p, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                            ctypes.POINTER(_i32)])
+_sig("gv_model_sphering", [_vp, _vp, _vp, _vp])
+_sig("gv_scan_plan", [_i64, _i64, _i32, ctypes.c_int, _i32, _i32, _i64, _i32, _vp, _i32, ctypes.POINTER(_i32),
+                      ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
 _sig("gv_profile_enable", [_i32])
 _sig("gv_tags", [_vp, _vp, _i64, _vp, _vp])
 _sig("gv_search_batched", [_i32, _vp, _vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_batch_release", [], None)
+_sig("gv_batch_counts", [ctypes.POINTER(_i64), ctypes.POINTER(_i64)], None)
 _sig("gv_moments", [_vp, _i64, _i32, _vp, _i32, _vp, _vp])
 _sig("gv_loss_grad", [_i32, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp])
 _sig("gv_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
@@ -155,6 +165,31 @@ class Model:
                                    _np_ptr(counts), _np_ptr(fb), ctypes.byref(it)), "gv_model_stats")
         return dict(KQ=KQ, KX=KX, lam_Q=lamQ, lam_c=lamc, counts=counts, fallback=fb.astype(bool),
                     iters=it.value)
+
+    def sphering(self):
+        """(W, W+, P) of a fitted model: D x D, D x D, C x d x D."""
+        W = np.empty((self.D, self.D)); Wp = np.empty((self.D, self.D)); P = np.empty((self.C, self.d, self.D))
+        _check(_lib.gv_model_sphering(self._h, _np_ptr(W), _np_ptr(Wp), _np_ptr(P)), "gv_model_sphering")
+        return W, Wp, P
+
+    def save(self, path: str):
+        """Write the model to a file (gv_model_save)."""
+        _check(_lib.gv_model_save(self._h, os.fsencode(path)), "gv_model_save")
+
+
+def model_load(path: str) -> Model:
+    """A model read from a file written by Model.save (gv_model_load)."""
+    h = _vp()
+    _check(_lib.gv_model_load(os.fsencode(path), ctypes.byref(h)), "gv_model_load")
+    return Model(h)
+
+
+def model_file_info(path: str):
+    """Validate a model file without the device: (C, d, D, has_stats)."""
+    C, d, D, st = _i32(), _i32(), _i32(), _i32()
+    _check(_lib.gv_model_file_info(os.fsencode(path), ctypes.byref(C), ctypes.byref(d), ctypes.byref(D),
+                                   ctypes.byref(st)), "gv_model_file_info")
+    return C.value, d.value, D.value, bool(st.value)
 
 
 class Index:
@@ -269,7 +304,7 @@ def project_flex(model: Model, fmt, Q, d_search: int):
     m = Q.shape[0]
     qc = torch.empty((m, model.C, padded_dim(model.d)), dtype=torch.float32, device=Q.device)
     t = torch.empty((m, model.C), dtype=torch.float32, device=Q.device)
-    qhat = torch.empty((m, model.C, padded_dim(d_search)), dtype=_elem_dtype(f), device=Q.device)
+    qhat = torch.empty((m, model.C, padded_dim(d_search)), dtype=_view_dtype(f), device=Q.device)
     _check(_lib.gv_project_flex(model._h, f, _ptr(Q), m, d_search, _ptr(qc), _ptr(t), _ptr(qhat), _stream()),
            "gv_project_flex")
     return qc, t, qhat
@@ -297,9 +332,11 @@ def rerank_stored(index: Index, qc, cand_ids, k: int):
     return ids, sc
 
 
-def _elem_dtype(fmt):
+def _view_dtype(fmt):
+    """Element type of the query views that meet storage format fmt (FP8 storage
+    meets FP16 views)."""
     import torch
-    return {FP32: torch.float32, FP16: torch.int16, BF16: torch.int16, FP8: torch.uint8}[fmt]
+    return {FP32: torch.float32, FP16: torch.int16, BF16: torch.int16, FP8: torch.int16}[fmt]
 
 
 def project(model: Model, fmt, Q, want_qc: bool = True):
@@ -311,7 +348,7 @@ def project(model: Model, fmt, Q, want_qc: bool = True):
     dp = padded_dim(model.d)
     qc = torch.empty((m, model.C, dp), dtype=torch.float32, device=Q.device) if want_qc else None
     t = torch.empty((m, model.C), dtype=torch.float32, device=Q.device)
-    qhat = torch.empty((m, model.C, dp), dtype=_elem_dtype(f), device=Q.device)
+    qhat = torch.empty((m, model.C, dp), dtype=_view_dtype(f), device=Q.device)
     _check(_lib.gv_project(model._h, f, _ptr(Q), m, _ptr(qc), _ptr(t), _ptr(qhat), _stream()), "gv_project")
     return qc, t, qhat
 
@@ -357,6 +394,11 @@ def host_eigh(A):
     return lam, Vt
 
 
+def eig_step_limit(max_steps: int = 0):
+    """QR step budget of one host eigendecomposition (0: the default, 60 x order)."""
+    _check(_lib.gv_eig_step_limit(int(max_steps)), "gv_eig_step_limit")
+
+
 def profile_enable(on: bool = True):
     _check(_lib.gv_profile_enable(1 if on else 0), "gv_profile_enable")
 
@@ -400,6 +442,13 @@ def search_batched(models, indexes, Qs, k: int, kappa: int, out=None):
 
 def batch_release():
     _lib.gv_batch_release()
+
+
+def batch_counts():
+    """(captures, replays) of gv_search_batched since the library was loaded."""
+    c, r = _i64(0), _i64(0)
+    _lib.gv_batch_counts(ctypes.byref(c), ctypes.byref(r))
+    return c.value, r.value
 
 
 def tags(model: Model, X):

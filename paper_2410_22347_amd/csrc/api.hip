@@ -1,5 +1,6 @@
 // C ABI of the library: argument validation, handle lifetime and the
 // sequencing of the device stages.  No exception crosses this boundary.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -12,6 +13,8 @@
 namespace gv {
 
 static thread_local std::string g_err;
+static std::atomic<uint64_t> g_handle_gen{0};
+uint64_t next_handle_gen() { return ++g_handle_gen; }
 static thread_local int g_splits = 0, g_qpw = 0, g_cap = 0;
 void set_error(const std::string& msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
@@ -85,12 +88,16 @@ gv_status guarded(F f) {
   }
 }
 
-bool valid(const gv_model* m) { return m && m->magic == kModelMagic; }
 bool valid(const gv_index* x) { return x && x->magic == kIndexMagic; }
+
+}  // namespace
+
+bool valid_model(const gv_model* m) { return m && m->magic == kModelMagic; }
 
 gv_status alloc_model(int C, int d, int D, gv_model** out) {
   gv_model* m = new gv_model();
   m->magic = kModelMagic;
+  m->gen = next_handle_gen();
   m->C = C;
   m->d = d;
   m->D = D;
@@ -110,6 +117,8 @@ gv_status alloc_model(int C, int d, int D, gv_model** out) {
   return GV_OK;
 }
 
+namespace {
+bool valid(const gv_model* m) { return valid_model(m); }
 }  // namespace
 
 gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite) {
@@ -144,6 +153,7 @@ const char* gv_status_string(gv_status s) {
     case GV_ENOTFIT: return "invalid or missing handle";
     case GV_ENONFINITE: return "non-finite input";
     case GV_EUNSUPPORTED: return "unsupported";
+    case GV_ENOCONV: return "eigensolver did not converge";
   }
   return "unknown status";
 }
@@ -271,6 +281,7 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
     gv_index* x = new gv_index();
     x->device = dev;
     x->magic = kIndexMagic;
+    x->gen = next_handle_gen();
     x->C = model->C;
     x->d = model->d;
     x->dp = pad_dim(model->d);
@@ -372,7 +383,7 @@ void gv_index_destroy(gv_index* x) {
 
 static gv_status check_search_args(const gv_index* idx, int64_t m, int32_t k, int32_t kappa) {
   GV_REQUIRE(m >= 0, "search: m < 0");
-  GV_REQUIRE(kappa >= 1 && kappa <= 256, "search: need 1 <= kappa <= 256");
+  GV_REQUIRE(kappa >= 1 && kappa <= kMaxKappa, "search: need 1 <= kappa <= 1024");
   GV_REQUIRE(k >= 1 && k <= kappa, "search: need 1 <= k <= kappa");
   GV_REQUIRE(kappa <= idx->n, "search: need kappa <= n");
   return GV_OK;
@@ -589,6 +600,7 @@ struct BatchGraph {
 };
 std::mutex g_batch_mu;
 BatchGraph g_batch;
+int64_t g_batch_captures = 0, g_batch_replays = 0;
 constexpr int kBatchStreams = 4;
 hipStream_t g_side[64][kBatchStreams] = {};
 hipStream_t g_origin[64] = {};  // captures start here (the caller's stream may be the legacy default stream)
@@ -644,14 +656,17 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
       GV_REQUIRE(m[i] == 0 || (Q[i] && out_ids[i]), "gv_search_batched: NULL query or output");
       if (m[i] > 0) GV_TRY(search_plan(md, ix, m[i], kappa, &plans[i]));
       if (m[i] > 0) slot[i % kBatchStreams] = std::max(slot[i % kBatchStreams], (plans[i].bytes + 255) / 256 * 256);
-      for (uintptr_t v : {(uintptr_t)md, (uintptr_t)ix, (uintptr_t)Q[i], (uintptr_t)m[i], (uintptr_t)out_ids[i],
-                          (uintptr_t)(out_scores ? out_scores[i] : nullptr)})
+      // handles enter the key by generation: a handle freed and another created at
+      // the same address must not replay a graph that holds the old one's buffers
+      for (uintptr_t v : {(uintptr_t)md->gen, (uintptr_t)ix->gen, (uintptr_t)Q[i], (uintptr_t)m[i],
+                          (uintptr_t)out_ids[i], (uintptr_t)(out_scores ? out_scores[i] : nullptr)})
         key.push_back(v);
     }
     hipStream_t st = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g_batch_mu);
     if (g_batch.exec && g_batch.key == key) {  // same batch as last time: replay
       GV_HIP(hipGraphLaunch(g_batch.exec, st));
+      ++g_batch_replays;
       return GV_OK;
     }
     release_batch(g_batch);
@@ -705,6 +720,7 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
     g_batch.exec = exec;
     g_batch.ws = ws;
     g_batch.device = dev;
+    ++g_batch_captures;
     GV_HIP(hipGraphLaunch(exec, st));
     return GV_OK;
   });
@@ -713,6 +729,30 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
 void gv_batch_release(void) {
   std::lock_guard<std::mutex> lk(g_batch_mu);
   release_batch(g_batch);
+}
+
+void gv_batch_counts(int64_t* captures, int64_t* replays) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  if (captures) *captures = g_batch_captures;
+  if (replays) *replays = g_batch_replays;
+}
+
+gv_status gv_scan_plan(int64_t n, int64_t n_pad, int32_t C, gv_format fmt, int32_t d, int32_t d_search, int64_t m,
+                       int32_t kappa, gv_scan_level* levels, int32_t max_levels, int32_t* n_levels, int64_t* list_keys,
+                       int64_t* scratch_bytes) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(n >= 1 && C >= 1 && C <= 255 && n_pad >= n && n_pad <= n + 31LL * C && n_pad % 32 == 0,
+               "gv_scan_plan: need n >= 1, 1 <= C <= 255, n <= n_pad <= n + 31 C, n_pad a multiple of 32");
+    GV_REQUIRE(fmt >= GV_FP32 && fmt <= GV_FP8_E4M3, "gv_scan_plan: unknown format");
+    GV_REQUIRE(d >= 1 && d_search >= 0 && d_search <= d, "gv_scan_plan: need d >= 1 and 0 <= d_search <= d");
+    GV_REQUIRE(m >= 1 && kappa >= 1 && kappa <= kMaxKappa && kappa <= n, "gv_scan_plan: need m >= 1, 1 <= kappa <= min(n, 1024)");
+    GV_REQUIRE(max_levels >= 0, "gv_scan_plan: max_levels < 0");
+    int nl = 0;
+    GV_TRY(scan_plan_describe(n, n_pad, C, fmt, d, d_search, m, kappa, levels, max_levels, &nl, list_keys,
+                              scratch_bytes));
+    if (n_levels) *n_levels = nl;
+    return GV_OK;
+  });
 }
 
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap) {
@@ -757,11 +797,21 @@ gv_status gv_host_eigh(int32_t n, const double* A, double* lam, double* Vt) {
   return guarded([&]() -> gv_status {
     GV_REQUIRE(n >= 1 && A && lam && Vt, "gv_host_eigh: bad arguments");
     std::vector<double> a(A, A + (size_t)n * n), l, v;
-    eigh_desc(n, a, l, v);
+    const bool ok = eigh_desc(n, a, l, v);
     std::memcpy(lam, l.data(), sizeof(double) * n);
     std::memcpy(Vt, v.data(), sizeof(double) * (size_t)n * n);
+    if (!ok) {
+      set_error("gv_host_eigh: the QR steps did not converge within the step budget");
+      return GV_ENOCONV;
+    }
     return GV_OK;
   });
+}
+
+gv_status gv_eig_step_limit(int32_t max_steps) {
+  if (max_steps < 0) return GV_EINVAL;
+  set_eig_step_limit(max_steps);
+  return GV_OK;
 }
 
 }  // extern "C"

@@ -14,6 +14,8 @@
 namespace gv {
 
 constexpr int kWave = 64;
+// largest kappa (candidates per query) of the select and rerank stages
+constexpr int kMaxKappa = 1024;
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
@@ -44,6 +46,10 @@ void clear_error();
 
 // ---------------------------------------------------------------- formats
 inline int fmt_bytes(int f) { return f == GV_FP32 ? 4 : (f == GV_FP8_E4M3 ? 1 : 2); }
+// Format of the query views that meet stored vectors of format f: the storage
+// format, except FP8 storage, which is scored against FP16 views (the matrix
+// core takes E4M3 widened exactly to FP16; FP16 x E4M3 products are exact).
+inline int view_fmt(int f) { return f == GV_FP8_E4M3 ? GV_FP16 : f; }
 
 // Matrix-core operand tiling of the stored reduced vectors.  Rows are grouped
 // by cluster, each cluster's segment padded to a multiple of 32 rows.  A tile
@@ -182,6 +188,7 @@ __host__ __device__ inline uint32_t key_id(uint64_t k) { return 0xFFFFFFFFu - (u
 // ---------------------------------------------------------------- handles
 struct gv_model {
   uint64_t magic;
+  uint64_t gen;  // unique per handle in the process (never reused, unlike its address)
   int C, d, D;
   int device;
   double* mu;  // device C x D
@@ -189,6 +196,7 @@ struct gv_model {
   double* B;   // device C*d x D
   bool fitted;
   std::vector<double> KQ, KX, lamQ, lamc;
+  std::vector<double> W, Wp, P;  // host D x D, D x D, C x d x D (fitted models)
   std::vector<int64_t> counts;
   std::vector<uint8_t> fallback;
   int iters;
@@ -196,6 +204,7 @@ struct gv_model {
 
 struct gv_index {
   uint64_t magic;
+  uint64_t gen;  // unique per handle in the process (never reused, unlike its address)
   int C, d, dp, D, fmt;
   int64_t n;       // database rows
   int64_t n_pad;   // stored rows: every cluster segment padded to a multiple of 32
@@ -217,6 +226,11 @@ constexpr uint64_t kModelMagic = 0x474C45414E4D4F44ull;  // "GLEANMOD"
 constexpr uint64_t kIndexMagic = 0x474C45414E494458ull;  // "GLEANIDX"
 
 namespace gv {
+// next handle generation (1, 2, ...): keys of kept state name handles by it
+uint64_t next_handle_gen();
+// a model handle with device storage for mu, A, B (shape C, d, D); fitted = false
+gv_status alloc_model(int C, int d, int D, gv_model** out);
+bool valid_model(const gv_model* m);
 // internal entry points shared between translation units
 gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, int d, int C,
                    uint64_t seed, const gv_fit_opts* opts, hipStream_t st, gv_model* model);
@@ -230,6 +244,9 @@ gv_status fit_from_stats_impl(const double* mu, const double* KQ, double m_q, co
 // views and the scan use (Section 3.3); q_c always holds all d of them.
 gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m, float* qc,
                        float* t, void* qhat, hipStream_t st, int d_search = 0);
+gv_status scan_plan_describe(int64_t n, int64_t n_pad, int C, int fmt, int d, int d_search, int64_t m, int kappa,
+                             gv_scan_level* levels, int max_levels, int* n_levels, int64_t* list_keys,
+                             int64_t* scratch_bytes);
 gv_status score_topk_impl(const gv_index* index, const void* qhat, const float* t, int64_t m,
                           int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st, int d_search = 0);
 void keep_pool(int device);
@@ -284,8 +301,10 @@ gv_status gemm_f64(int64_t M, int64_t N, int64_t K, GemmOperand<TA> a, GemmOpera
 
 // host symmetric eigensolver (Householder tridiagonalisation + implicit QL/QR)
 // A: n x n symmetric (row-major, overwritten); lam: n eigenvalues decreasing;
-// Vt: n x n, row r = unit eigenvector of lam[r].
-void eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Vt);
+// Vt: n x n, row r = unit eigenvector of lam[r].  Returns false if the QR steps
+// did not converge within the step budget (set_eig_step_limit).
+bool eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Vt);
+void set_eig_step_limit(long max_steps);
 
 int tuned_splits();
 int tuned_qpw();

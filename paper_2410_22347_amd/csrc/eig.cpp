@@ -11,22 +11,29 @@
 //      chasing with Givens rotations), deflating negligible off-diagonals,
 //      the rotations being applied to the rows of Q^T.
 // Rows of the returned Vt are unit eigenvectors, sorted by decreasing
-// eigenvalue.  Written for clarity and cache-friendly row updates; all
+// eigenvalue.  Returns false when an off-diagonal entry is still above the
+// deflation threshold after the step budget (60 steps per order by default).  Written for clarity and cache-friendly row updates; all
 // clusters are solved in parallel by the caller.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <numeric>
 #include <vector>
 
 namespace gv {
 
-void eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Vt) {
+// QR steps allowed per decomposition before the solver reports failure
+// (0: 60 per matrix order)
+static std::atomic<long> g_step_limit{0};
+void set_eig_step_limit(long max_steps) { g_step_limit = max_steps > 0 ? max_steps : 0; }
+
+bool eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Vt) {
   lam.assign(n, 0.0);
   Vt.assign((size_t)n * n, 0.0);
   if (n == 1) {
     lam[0] = A[0];
     Vt[0] = 1.0;
-    return;
+    return true;
   }
   auto a_ = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
 
@@ -117,7 +124,8 @@ void eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vec
   };
   int hi = n - 1;
   long guard = 0;
-  const long max_steps = 60L * n;
+  const long lim = g_step_limit.load();
+  const long max_steps = lim > 0 ? lim : 60L * n;
   while (hi > 0 && guard < max_steps) {
     if (std::fabs(off[hi - 1]) <= eps * (std::fabs(diag[hi - 1]) + std::fabs(diag[hi]))) {
       off[hi - 1] = 0.0;
@@ -158,6 +166,7 @@ void eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vec
     }
     ++guard;
   }
+  const bool converged = hi == 0;
 
   // ---------------------------------------------------------- sort decreasing
   std::vector<int> order(n);
@@ -169,6 +178,7 @@ void eigh_desc(int n, std::vector<double>& A, std::vector<double>& lam, std::vec
     std::copy(&Vt[(size_t)order[r] * n], &Vt[(size_t)order[r] * n] + n, &sorted[(size_t)r * n]);
   }
   Vt.swap(sorted);
+  return converged;
 }
 
 }  // namespace gv

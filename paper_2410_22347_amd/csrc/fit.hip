@@ -176,7 +176,10 @@ gv_status sphere_project(gv_model* model, const double* KX_dev, const std::vecto
   DevBuf<double> W, Wp, tmp, Y;
   // ------------------------------------------------ sphering: W, W+
   std::vector<double> Aq(model->KQ), lamQ, Uq;
-  eigh_desc(D, Aq, lamQ, Uq);
+  if (!eigh_desc(D, Aq, lamQ, Uq)) {
+    set_error("fit: the eigendecomposition of K_Q did not converge");
+    return GV_ENOCONV;
+  }
   const double rcond = (double)D * 0x1.0p-52;
   std::vector<double> VS(DD), VSp(DD);
   for (int r = 0; r < D; ++r) {
@@ -241,6 +244,7 @@ gv_status sphere_project(gv_model* model, const double* KX_dev, const std::vecto
   std::vector<int> jobs;
   for (int c = 0; c < nY; ++c)
     if (c == C || !fallback[c]) jobs.push_back(c);
+  std::vector<uint8_t> converged(nY, 1);
   parallel_for((int)jobs.size(), [&](int ji) {
     int c = jobs[ji];
     std::vector<double> Ysym(DD);
@@ -248,12 +252,18 @@ gv_status sphere_project(gv_model* model, const double* KX_dev, const std::vecto
     for (int i = 0; i < D; ++i)
       for (int j = 0; j < D; ++j) Ysym[(size_t)i * D + j] = 0.5 * (y[(size_t)i * D + j] + y[(size_t)j * D + i]);
     std::vector<double> lam, Vt;
-    eigh_desc(D, Ysym, lam, Vt);
+    converged[c] = eigh_desc(D, Ysym, lam, Vt) ? 1 : 0;
     Vt.resize((size_t)d * D);
     canonical_signs(Vt.data(), d, D);
     lam_all[c] = std::move(lam);
     P_all[c] = std::move(Vt);
   });
+  for (int c = 0; c < nY; ++c) {
+    if (!converged[c]) {
+      set_error("fit: the eigendecomposition of W K_c W did not converge for cluster " + std::to_string(c));
+      return GV_ENOCONV;
+    }
+  }
   for (int c = 0; c < C; ++c) {
     int src = fallback[c] ? C : c;
     std::copy(P_all[src].begin(), P_all[src].end(), P.begin() + (size_t)c * d * D);
@@ -270,8 +280,13 @@ gv_status sphere_project(gv_model* model, const double* KX_dev, const std::vecto
   GV_TRY(gemm_f64<double, double>((int64_t)C * d, D, D, p_op, w_op, Epi::StoreF64,
                                   GemmOut{model->B, D, 0, 0, nullptr}, st));
   GV_HIP(hipMemcpyAsync(model->mu, mu_dev, sizeof(double) * C * D, hipMemcpyDeviceToDevice, st));
+  model->W.resize(DD);
+  model->Wp.resize(DD);
+  GV_HIP(hipMemcpyAsync(model->W.data(), W.p, sizeof(double) * DD, hipMemcpyDeviceToHost, st));
+  GV_HIP(hipMemcpyAsync(model->Wp.data(), Wp.p, sizeof(double) * DD, hipMemcpyDeviceToHost, st));
   GV_HIP(hipStreamSynchronize(st));
 
+  model->P = std::move(P);
   model->lamQ = lamQ;
   model->lamc = lamc;
   model->counts = counts;

@@ -14,8 +14,8 @@ namespace gv {
 namespace {
 
 // One wavefront per (query, cluster): zero-pads q_c (row pitch dq) past its d
-// values; the power-of-two scale t of its first ds values and the
-// storage-format view rnd(q_c / t) of them (row pitch dpo, zero padded).
+// values; the power-of-two scale t of its first ds values and the view
+// rnd(q_c / t) of them in view format FMT (row pitch dpo, zero padded).
 template <int FMT>
 __global__ void k_quant_queries(float* __restrict__ qc, int64_t m, int C, int d, int dq, int ds, int dpo, double T,
                                 float* __restrict__ t_out, void* __restrict__ qhat) {
@@ -34,8 +34,7 @@ __global__ void k_quant_queries(float* __restrict__ qc, int64_t m, int C, int d,
     const double y = (double)x / (double)t;  // exact: t is a power of two
     if (FMT == GV_FP32) ((float*)qhat)[w * dpo + j] = x;
     else if (FMT == GV_FP16) ((uint16_t*)qhat)[w * dpo + j] = to_fp16(y);
-    else if (FMT == GV_BF16) ((uint16_t*)qhat)[w * dpo + j] = to_bf16(y);
-    else ((uint8_t*)qhat)[w * dpo + j] = to_fp8(y);
+    else ((uint16_t*)qhat)[w * dpo + j] = to_bf16(y);
   }
 }
 
@@ -85,12 +84,12 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
   }
   if (s == GV_OK) {
     const unsigned grid = (unsigned)((m * C + 3) / 4);
-    const double T = scale_target(fmt);
-    switch (fmt) {
+    const int vf = view_fmt(fmt);  // FP8 storage meets FP16 views
+    const double T = scale_target(vf);
+    switch (vf) {
       case GV_FP32: hipLaunchKernelGGL(k_quant_queries<GV_FP32>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
       case GV_FP16: hipLaunchKernelGGL(k_quant_queries<GV_FP16>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
-      case GV_BF16: hipLaunchKernelGGL(k_quant_queries<GV_BF16>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
-      default: hipLaunchKernelGGL(k_quant_queries<GV_FP8_E4M3>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
+      default: hipLaunchKernelGGL(k_quant_queries<GV_BF16>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
     }
   }
   if (tmp) GV_HIP(hipFreeAsync(tmp, st));
@@ -137,6 +136,35 @@ __global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ 
 // fewer exist).  Otherwise: seed[q] = max(seed[q], kappa-th best score).
 constexpr int kSelWin = 4096;
 constexpr int kMaxLists = 4096;
+static_assert(kMaxKappa <= kSelWin / 2, "a select window holds the kappa kept keys and as many new ones");
+
+// bitonic sort, descending, of the first `size` entries (a power of two) of
+// key[] in LDS by every thread of the workgroup (nthreads threads)
+template <typename T>
+__device__ void block_sort_desc(T* key, int size, int nthreads) {
+  for (int k = 2; k <= size; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < size; i += nthreads) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool desc = (i & k) == 0;
+          const T x = key[i], y = key[l];
+          if (desc ? (x < y) : (x > y)) {
+            key[i] = y;
+            key[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__host__ __device__ inline int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
 
 template <bool FINAL>
 __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf, const int32_t* __restrict__ cnt,
@@ -145,7 +173,7 @@ __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf
                                                 float* __restrict__ out_scores) {
   __shared__ uint64_t keys[kSelWin];
   __shared__ int32_t pre[kMaxLists + 1];
-  __shared__ uint64_t stage[256];
+  __shared__ uint64_t stage[kMaxKappa];
   __shared__ int32_t wsum[4];
   __shared__ uint32_t s_kept;
   __shared__ SelectSmem sel;
@@ -228,27 +256,15 @@ __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf
     }
     return;
   }
-  // bitonic sort of 256 keys, descending (padding keys are 0)
-  stage[tid] = tid < kept ? keys[tid] : 0;
+  // bitonic sort of the kept keys, descending (padding keys are 0)
+  const int sn = pow2_at_least(kappa);
+  for (int i = tid; i < sn; i += 256) stage[i] = i < kept ? keys[i] : 0;
   __syncthreads();
-  for (int size = 2; size <= 256; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const int i = tid, j = i ^ stride;
-      if (j > i) {
-        const bool desc = (i & size) == 0;
-        const uint64_t x = stage[i], y = stage[j];
-        if (desc ? (x < y) : (x > y)) {
-          stage[i] = y;
-          stage[j] = x;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  if (tid < kappa) {
-    const uint64_t k = stage[tid];
-    out_ids[q * kappa + tid] = (int32_t)key_id(k);
-    out_scores[q * kappa + tid] = key_score(k);
+  block_sort_desc(stage, sn, 256);
+  for (int i = tid; i < kappa; i += 256) {
+    const uint64_t k = stage[i];
+    out_ids[q * kappa + i] = (int32_t)key_id(k);
+    out_scores[q * kappa + i] = key_score(k);
   }
 }
 
@@ -338,7 +354,9 @@ namespace {
 struct ScanPlan {
   std::vector<int64_t> levels;
   std::vector<Shape> shapes;
+  std::vector<ScanLimits> limits;
   bool has_dense = false;
+  uint64_t keys = 0;  // list slots of the scratch (m x Rmax x cap)
   int Rmax = 1;
   int64_t ns = 0;
   int cap = kCap;
@@ -348,9 +366,35 @@ struct ScanPlan {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int d_search = 0) {
-  p->dp = pad_dim(d_search > 0 ? d_search : idx->d);
-  if (p->dp > idx->dp || p->dp > 256) {
+// the k_scan instantiation a shape launches, described on the host
+template <int FMT>
+ScanLimits limits_fmt(int dp, const Shape& sh) {
+  constexpr int km = MfmaOp<FMT>::KM;
+  switch (dp / km) {
+    case 32 / km: return limits_for_shape<FMT, 32 / km>(sh);
+    case 64 / km: return limits_for_shape<FMT, 64 / km>(sh);
+    case 128 / km: return limits_for_shape<FMT, 128 / km>(sh);
+    case 160 / km: return limits_for_shape<FMT, 160 / km>(sh);
+    case 192 / km: return limits_for_shape<FMT, 192 / km>(sh);
+    default: return limits_for_shape<FMT, 256 / km>(sh);
+  }
+}
+ScanLimits scan_limits(int fmt, int dp, const Shape& sh) {
+  switch (fmt) {
+    case GV_FP32: return limits_fmt<GV_FP32>(dp, sh);
+    case GV_FP16: return limits_fmt<GV_FP16>(dp, sh);
+    case GV_BF16: return limits_fmt<GV_BF16>(dp, sh);
+    default: return limits_fmt<GV_FP8_E4M3>(dp, sh);
+  }
+}
+
+// The launch plan of S2/S3 from the index dimensions alone: n rows stored as
+// n_pad (segments padded to whole tiles), C clusters, format, stored padded
+// length dps, leading length dp_search scanned.
+gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int d_search, int64_t m, int kappa,
+                         ScanPlan* p) {
+  p->dp = pad_dim(d_search);
+  if (p->dp > dps || p->dp > 256) {
     set_error("the scan reads at most the leading 256 stored coordinates (padded), and no more than the index stores");
     return GV_EUNSUPPORTED;
   }
@@ -359,16 +403,31 @@ gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int 
     set_error("candidate list capacity must lie in [kappa + 417, 2048]");
     return GV_EINVAL;
   }
-  p->levels = cascade(idx->n, kappa);
+  p->levels = cascade(n, kappa);
   p->has_dense = p->levels.size() > 1;
-  const int64_t ntiles = idx->n_pad / kRows;
+  const int64_t ntiles = n_pad / kRows;
   p->shapes.clear();
+  p->limits.clear();
   p->Rmax = 1;
   for (size_t li = 0; li < p->levels.size(); ++li) {
     const int64_t s = p->levels[li];
-    const Shape sh = choose_shape(idx->fmt, p->dp, m, (ntiles + s - 1) / s * kRows, idx->C);
-    if (!(p->has_dense && li == 0)) p->Rmax = std::max(p->Rmax, sh.R);  // the dense scan writes no lists
+    const Shape sh = choose_shape(fmt, p->dp, m, (ntiles + s - 1) / s * kRows, C);
+    const ScanLimits lm = scan_limits(fmt, p->dp, sh);
+    const bool dense = p->has_dense && li == 0;  // the dense scan writes no lists
+    if (!dense) {
+      p->Rmax = std::max(p->Rmax, sh.R);
+      // a list is compacted once it holds more than lim keys and may then grow
+      // by 32 keys per tile for U + 1 tiles before the next check: the staging
+      // (CAPL) and the list (cap) must hold that, and a compaction to the kappa
+      // best must leave room (lim > kappa)
+      const int lim = std::min(p->cap, lm.CAPL) - kRows * (lm.U + 1);
+      if (lim <= kappa) {
+        set_error("kappa too large for the candidate lists of this launch shape (reduce kappa or raise the list cap)");
+        return GV_EUNSUPPORTED;
+      }
+    }
     p->shapes.push_back(sh);
+    p->limits.push_back(lm);
   }
   p->ns = p->has_dense ? ((ntiles + p->levels[0] - 1) / p->levels[0]) * kRows : 0;
   const uint64_t keys = (uint64_t)m * p->Rmax * p->cap;
@@ -376,6 +435,7 @@ gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int 
     set_error("search batch too large for the candidate lists (reduce m)");
     return GV_EUNSUPPORTED;
   }
+  p->keys = keys;
   size_t o = 0;
   p->off_buf = o;   o = align256(o + sizeof(uint64_t) * keys);
   p->off_cnt = o;   o = align256(o + sizeof(int32_t) * m * p->Rmax);
@@ -383,6 +443,10 @@ gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int 
   p->off_dense = o; o = align256(o + (p->has_dense ? sizeof(float) * m * p->ns : 0));
   p->bytes = o;
   return GV_OK;
+}
+
+gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int d_search = 0) {
+  return plan_scan_dims(idx->n, idx->n_pad, idx->C, idx->fmt, idx->dp, d_search > 0 ? d_search : idx->d, m, kappa, p);
 }
 
 gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const void* qhat, const float* t, int64_t m,
@@ -454,6 +518,38 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
 
 }  // namespace
 
+gv_status scan_plan_describe(int64_t n, int64_t n_pad, int C, int fmt, int d, int d_search, int64_t m, int kappa,
+                             gv_scan_level* levels, int max_levels, int* n_levels, int64_t* list_keys,
+                             int64_t* scratch_bytes) {
+  ScanPlan p;
+  GV_TRY(plan_scan_dims(n, n_pad, C, fmt, pad_dim(d), d_search > 0 ? d_search : d, m, kappa, &p));
+  const int nl = (int)p.levels.size();
+  if (n_levels) *n_levels = nl;
+  if (list_keys) *list_keys = (int64_t)p.keys;
+  if (scratch_bytes) *scratch_bytes = (int64_t)p.bytes;
+  for (int li = 0; li < nl && li < max_levels && levels; ++li) {
+    const Shape& sh = p.shapes[li];
+    const ScanLimits& lm = p.limits[li];
+    gv_scan_level& o = levels[li];
+    o.stride = p.levels[li];
+    o.dense = (p.has_dense && li == 0) ? 1 : 0;
+    o.ranges = sh.R;
+    o.grid = sh.grid;
+    o.query_blocks = sh.nqb;
+    o.queries_per_wave = 32 * lm.nb;
+    o.shared = sh.shared ? 1 : 0;
+    o.xcd_map = sh.xcd_map;
+    o.tile_ring = lm.ring ? 1 : 0;
+    o.workgroups_per_cu = lm.occupancy;
+    o.check_every = lm.U;
+    o.staging = lm.CAPL;
+    o.list_cap = p.cap;
+    o.list_limit = std::min(p.cap, lm.CAPL) - kRows * (lm.U + 1);
+    o.rows_per_level = (n_pad / kRows + p.levels[li] - 1) / p.levels[li] * kRows;
+  }
+  return GV_OK;
+}
+
 gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t, int64_t m, int kappa,
                           int32_t* cand_ids, float* cand_scores, hipStream_t st, int d_search) {
   if (m == 0) return GV_OK;
@@ -483,7 +579,7 @@ gv_status search_plan(const gv_model* model, const gv_index* idx, int64_t m, int
   }
   sp->d_search = d_search;
   sp->stored = stored;
-  const size_t C = idx->C, dp = idx->dp, eb = fmt_bytes(idx->fmt);
+  const size_t C = idx->C, dp = idx->dp, eb = fmt_bytes(view_fmt(idx->fmt));
   size_t o = 0;
   sp->off_t = o;    o = align256(o + sizeof(float) * m * C);
   sp->off_qc = o;   o = align256(o + sizeof(float) * m * C * dp);
@@ -523,7 +619,7 @@ namespace {
 // candidate rows at a time so their loads are in flight together.
 constexpr int kRerankThreads = 1024;
 
-__device__ void sort_emit(double* s_score, int32_t* s_id, int64_t q, int k, int32_t* __restrict__ out_ids,
+__device__ void sort_emit(double* s_score, int32_t* s_id, int64_t q, int kappa, int k, int32_t* __restrict__ out_ids,
                           float* __restrict__ out_scores);
 
 __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restrict__ X, int64_t n, int D,
@@ -531,15 +627,15 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restri
                                                            const int32_t* __restrict__ cand, int kappa, int k,
                                                            int32_t* __restrict__ out_ids,
                                                            float* __restrict__ out_scores) {
-  __shared__ double s_score[256];
-  __shared__ int32_t s_id[256];
+  __shared__ double s_score[kMaxKappa];
+  __shared__ int32_t s_id[kMaxKappa];
   constexpr int W = kRerankThreads / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t q = blockIdx.x;
   const float* qv = Q + q * D;
-  if (tid < 256) {
-    s_score[tid] = -INFINITY;
-    s_id[tid] = 0x7fffffff;
+  for (int i = tid; i < kMaxKappa; i += kRerankThreads) {
+    s_score[i] = -INFINITY;
+    s_id[i] = 0x7fffffff;
   }
   __syncthreads();
   // exact <q, x> with FP64 accumulation of exact FP32 x FP32 products
@@ -570,18 +666,20 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restri
     }
   }
   __syncthreads();
-  sort_emit(s_score, s_id, q, k, out_ids, out_scores);
+  sort_emit(s_score, s_id, q, kappa, k, out_ids, out_scores);
 }
 
-// bitonic sort of 256 (score, id) pairs in LDS (score desc, then id asc), then
-// the first k to the output row q; called by every thread of the workgroup
-__device__ void sort_emit(double* s_score, int32_t* s_id, int64_t q, int k, int32_t* __restrict__ out_ids,
+// bitonic sort of the (score, id) pairs in LDS (score desc, then id asc) over
+// the smallest power of two >= kappa slots (unused slots hold -inf), then the
+// first k to the output row q; called by every thread of the workgroup
+__device__ void sort_emit(double* s_score, int32_t* s_id, int64_t q, int kappa, int k, int32_t* __restrict__ out_ids,
                           float* __restrict__ out_scores) {
   const int tid = threadIdx.x;
-  for (int size = 2; size <= 256; size <<= 1) {
+  const int sn = pow2_at_least(kappa);
+  for (int size = 2; size <= sn; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      if (tid < 256) {
-        const int i = tid, j = i ^ stride;
+      for (int i = tid; i < sn; i += kRerankThreads) {
+        const int j = i ^ stride;
         if (j > i) {
           const bool desc = (i & size) == 0;
           const double xs = s_score[i], ys = s_score[j];
@@ -615,16 +713,16 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank_stored(
     const int32_t* __restrict__ pos, int64_t n, int C, const float* __restrict__ qc,
     const int32_t* __restrict__ cand, int kappa, int k, int32_t* __restrict__ out_ids,
     float* __restrict__ out_scores) {
-  __shared__ double s_score[256];
-  __shared__ int32_t s_id[256];
+  __shared__ double s_score[kMaxKappa];
+  __shared__ int32_t s_id[kMaxKappa];
   constexpr int W = kRerankThreads / 64;
   constexpr int EPL = FMT == GV_FP32 ? 1 : 8, KM = FMT == GV_FP32 ? 2 : 16;
   constexpr int EB = FMT == GV_FP32 ? 4 : (FMT == GV_FP8_E4M3 ? 1 : 2);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t q = blockIdx.x;
-  if (tid < 256) {
-    s_score[tid] = -INFINITY;
-    s_id[tid] = 0x7fffffff;
+  for (int i = tid; i < kMaxKappa; i += kRerankThreads) {
+    s_score[i] = -INFINITY;
+    s_id[i] = 0x7fffffff;
   }
   __syncthreads();
   const int groups = dps / EPL;
@@ -665,7 +763,7 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank_stored(
     }
   }
   __syncthreads();
-  sort_emit(s_score, s_id, q, k, out_ids, out_scores);
+  sort_emit(s_score, s_id, q, kappa, k, out_ids, out_scores);
 }
 
 }  // namespace

@@ -14,14 +14,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // Per-format operand of v_mfma_f32_32x32x{16,2}: each lane holds EPL
 // consecutive k of one row (A) or one query (B); lanes 32..63 hold the next EPL.
 // S is the stored type loaded from memory, T the matrix-core operand, cvt the
-// (exact) conversion and kScale the factor cvt applies to each value.
+// (exact) conversion and kScale the factor cvt applies to each stored value.
+// The query view (B) is stored as QS, QEB bytes per element, and reaches the
+// matrix core unchanged.
 //
 // FP8-E4M3 storage is widened to FP16 in registers: placing the sign in bit 15
 // and the exponent and fraction fields in bits 7..13 gives, for every finite
 // E4M3 code (normal or subnormal), exactly the E4M3 value times 2^-8.  The
-// FP16 matrix core then forms exact products with FP32 accumulation.  (With
-// the dedicated FP8 x FP8 matrix-core form, scores fell outside the FP32
-// forward-error bound in the parity tests.)
+// FP16 matrix core then multiplies it with the FP16 query view: the products
+// (11 x 4 significant bits) are exact, accumulated in FP32.
 template <int FMT>
 struct MfmaOp;
 
@@ -29,7 +30,8 @@ template <>
 struct MfmaOp<GV_FP32> {
   using S = float;
   using T = float;
-  static constexpr int KM = 2, EPL = 1, EB = 4;
+  using QS = float;
+  static constexpr int KM = 2, EPL = 1, EB = 4, QEB = 4;
   static constexpr float kScale = 1.0f;
   __device__ static inline T cvt(S v) { return v; }
   __device__ static inline f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
@@ -38,7 +40,8 @@ template <>
 struct MfmaOp<GV_FP16> {
   using S = f16x8;
   using T = f16x8;
-  static constexpr int KM = 16, EPL = 8, EB = 2;
+  using QS = f16x8;
+  static constexpr int KM = 16, EPL = 8, EB = 2, QEB = 2;
   static constexpr float kScale = 1.0f;
   __device__ static inline T cvt(S v) { return v; }
   __device__ static inline f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
@@ -47,7 +50,8 @@ template <>
 struct MfmaOp<GV_BF16> {
   using S = bf16x8;
   using T = bf16x8;
-  static constexpr int KM = 16, EPL = 8, EB = 2;
+  using QS = bf16x8;
+  static constexpr int KM = 16, EPL = 8, EB = 2, QEB = 2;
   static constexpr float kScale = 1.0f;
   __device__ static inline T cvt(S v) { return v; }
   __device__ static inline f32x16 mma(T a, T b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
@@ -66,7 +70,8 @@ template <>
 struct MfmaOp<GV_FP8_E4M3> {
   using S = u32x2;
   using T = f16x8;
-  static constexpr int KM = 16, EPL = 8, EB = 1;
+  using QS = f16x8;
+  static constexpr int KM = 16, EPL = 8, EB = 1, QEB = 2;
   static constexpr float kScale = 0.00390625f;  // 2^-8
   __device__ static inline T cvt(S v) {
     u32x4 h;

@@ -49,7 +49,7 @@ struct ScoreArgs {
   const float* scale;      // C
   const int64_t* offsets;  // C + 1 padded segment starts (stored rows)
   const int64_t* seg_end;  // C: first padding row of each segment
-  const uint8_t* qhat;     // m x C x dp, storage format
+  const uint8_t* qhat;     // m x C x dp, view format (view_fmt of the storage format)
   const float* qscale;     // m x C
   const float* seed;       // m initial thresholds, or null (-inf)
   uint64_t* buf;           // kFilter: m x R lists of cap keys
@@ -268,6 +268,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   constexpr int TB = KS * kblock_c;                 // bytes of one tile
 
   // two workgroups per CU, or an LDS tile ring, need the smaller compaction staging
+  // (KernelCfg states the same constants for the host-side plan checks)
   constexpr int CAPL = (OCC >= 2 || WGT) ? kCap / 2 : kCap;
   static_assert(CAPL - kRows * (U + 1) >= 256 + kRows, "the staging must hold kappa <= 256 plus a tile");
   __shared__ WaveSmem<QW, CAPL> s_wave[4];
@@ -453,17 +454,17 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
     const int64_t v1 = std::min<int64_t>(v_end, (tiles_end + stride - 1) / stride);
     const int64_t real_end = uniform64(a.seg_end[c]);
     {
-      const float sc = uniformf(a.scale[c]) * (1.0f / (Op::kScale * Op::kScale));
+      const float sc = uniformf(a.scale[c]) * (1.0f / Op::kScale);
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
         constexpr int nb = decltype(nbc)::value;
         const int64_t q = q0 + nb * 32 + col;
         const bool qv = q < a.m;
-        const uint8_t* qp = a.qhat + ((qv ? q : 0) * a.C + c) * (int64_t)a.dp * Op::EB +
-                            (int64_t)(half * Op::EPL) * Op::EB;
+        const uint8_t* qp = a.qhat + ((qv ? q : 0) * a.C + c) * (int64_t)a.dp * Op::QEB +
+                            (int64_t)(half * Op::EPL) * Op::QEB;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          const S raw = *(const S*)(qp + (int64_t)(s * Op::KM) * Op::EB);
-          bq[nb][s] = qv ? Op::cvt(raw) : zero_op<T>();
+          const typename Op::QS raw = *(const typename Op::QS*)(qp + (int64_t)(s * Op::KM) * Op::QEB);
+          bq[nb][s] = qv ? raw : zero_op<T>();
         }
         st[nb] = sc * (qv ? a.qscale[q * a.C + c] : 1.0f);
         inv_st[nb] = 1.0f / st[nb];
@@ -694,24 +695,65 @@ struct RingCfg {
   static constexpr int PL = TB <= 10240 ? 5 : 4;
 };
 
-// With two query blocks per wavefront on the LDS ring, two workgroups share a
-// CU (two wavefronts per SIMD, 256 registers each): one wavefront's filter,
-// barrier and LDS waits overlap the other's matrix-core chain.  Its ring is four
-// tiles deep and its compaction staging 1024 keys, so two workgroups fit the LDS
-// (tiles up to 10 KiB).
+// Compile-time configuration of one k_scan instantiation, shared by the launch
+// and by the host-side plan checks (scan_limits).  With two query blocks per
+// wavefront on the LDS ring, two workgroups share a CU (two wavefronts per SIMD,
+// 256 registers each): one wavefront's filter, barrier and LDS waits overlap the
+// other's matrix-core chain.  Its ring is four tiles deep and its compaction
+// staging 1024 keys, so two workgroups fit the LDS (tiles up to 10 KiB).
+template <int FMT, int KS, int NB, bool SHARED>
+struct KernelCfg {
+  using Cfg = ScanCfg<FMT, KS, NB>;
+  static constexpr bool W = !SHARED && RingCfg<FMT, KS>::ok;  // workgroup-shared LDS tile ring
+  static constexpr int OC = (W && NB == 2) ? 2 : 1;             // workgroups per CU
+  static constexpr int PL = W ? (OC == 2 ? 4 : RingCfg<FMT, KS>::PL) : 1;
+  static constexpr bool DEF = W || Cfg::defer;
+  static constexpr int P = Cfg::P;
+  // tiles between two overflow checks of a list (the kernel's unrolled steps)
+  static constexpr int U = W ? 2 : (DEF ? 2 * P : P);
+  // keys a compaction can stage in the wavefront's LDS
+  static constexpr int CAPL = (OC >= 2 || W) ? kCap / 2 : kCap;
+};
+
 template <int FMT, int KS, int NB, bool SHARED, int MODE>
 void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
-  using Cfg = ScanCfg<FMT, KS, NB>;
-  constexpr bool W = !SHARED && RingCfg<FMT, KS>::ok;
-  constexpr int OC = (W && NB == 2) ? 2 : 1;
-  constexpr int PL = W ? (OC == 2 ? 4 : RingCfg<FMT, KS>::PL) : 1;
-  constexpr bool DEF = W || Cfg::defer;
+  using K = KernelCfg<FMT, KS, NB, SHARED>;
   if (MODE == kFilter && args.stride == 1)
-    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, DEF, OC, true, W, PL>), dim3(sh.grid), dim3(256), 0,
-                       st, args);
+    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, K::P, K::DEF, K::OC, true, K::W, K::PL>), dim3(sh.grid),
+                       dim3(256), 0, st, args);
   else
-    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, Cfg::P, DEF, OC, false, W, PL>), dim3(sh.grid), dim3(256),
-                       0, st, args);
+    hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, K::P, K::DEF, K::OC, false, K::W, K::PL>), dim3(sh.grid),
+                       dim3(256), 0, st, args);
+}
+
+// The instantiation launch_score picks for a shape, described on the host.
+struct ScanLimits {
+  int nb = 0, U = 0, CAPL = 0, P = 0, PL = 0, occupancy = 0;
+  bool ring = false, defer = false;
+};
+
+template <int FMT, int KS, int NB, bool SHARED>
+ScanLimits limits_of() {
+  using K = KernelCfg<FMT, KS, NB, SHARED>;
+  ScanLimits l;
+  l.nb = NB; l.U = K::U; l.CAPL = K::CAPL; l.P = K::P; l.PL = K::PL; l.occupancy = K::OC;
+  l.ring = K::W; l.defer = K::DEF;
+  return l;
+}
+
+// mirrors launch_score's choice of NB and SHARED
+template <int FMT, int KS>
+ScanLimits limits_for_shape(const Shape& sh) {
+  if constexpr (FMT == GV_FP32) {
+    return sh.shared ? limits_of<FMT, KS, 1, true>() : limits_of<FMT, KS, 1, false>();
+  } else {
+    if (sh.shared && sh.nb == 1) return limits_of<FMT, KS, 1, true>();
+    if (sh.shared) return limits_of<FMT, KS, 2, true>();
+    if constexpr (KS <= 10) {
+      if (sh.nb == 4) return limits_of<FMT, KS, 4, false>();
+    }
+    return limits_of<FMT, KS, 2, false>();
+  }
 }
 
 template <int FMT, int KS, int MODE>

@@ -85,6 +85,65 @@ def test_batched_equals_single_and_replays(gv, collections):
     gv.batch_release()
 
 
+def test_batched_collections_match_oracle(gv, collections):
+    """Each collection of the batch against the oracle: the batched result equals the
+    single search bit for bit, and the single search passes the oracle parity of
+    verify_search (every difference from the oracle's encode and search of the same
+    rows, with the model's exported projections, proven a near tie)."""
+    from helpers import verify_search
+    from oracle import gleanvec as G
+    k, kappa = 10, 40
+    models = [b[1] for b in collections]
+    indexes = [b[2] for b in collections]
+    Qs = [b[3] for b in collections]
+    out = gv.search_batched(models, indexes, Qs, k, kappa)
+    torch.cuda.synchronize()
+    for j, (c, md, ix, Q) in enumerate(collections):
+        if Q.shape[0] == 0:
+            continue
+        _say(f"[batched] collection {j}: n={c.n} D={c.D} d={c.d} C={c.C} m={c.m}")
+        ids, sc = gv.search(md, ix, Q, k, kappa)
+        torch.cuda.synchronize()
+        assert torch.equal(out[j][0], ids) and torch.equal(out[j][1], sc)
+        geom = synth.make_geometry(c.cfg, c.D, c.C, "mixture")
+        X = synth.database(geom, c.n)
+        mu, A, B = md.export()
+        oi = G.encode(mu, B, X, "bf16")
+        Qh = Q.cpu().numpy()
+        ora = G.search(oi, A, Qh, k, kappa)
+        verify_search(gv, md, ix, X, Qh, oi, ora, kappa, k, "bf16", f"collection {j}")
+    gv.batch_release()
+
+
+def test_batched_recaptures_after_an_index_is_replaced(gv, collections):
+    """A replay key names handles by generation, not address: destroying an index
+    and encoding another (glibc often hands the freed address to the new handle)
+    must lead to a new capture whose results equal the single searches."""
+    k, kappa = 10, 40
+    c, md, ix, Q = collections[3]
+    geom = synth.make_geometry(c.cfg, c.D, c.C, "mixture")
+    X = torch.from_numpy(synth.database(geom, c.n)).cuda()
+    ix1 = gv.encode(md, X, "bf16", copy_X=True)
+    out = gv.search_batched([md], [ix1], [Q], k, kappa)
+    torch.cuda.synchronize()
+    cap0, rep0 = gv.batch_counts()
+    out = gv.search_batched([md], [ix1], [Q], k, kappa, out=out)   # same arguments: a replay
+    torch.cuda.synchronize()
+    cap1, rep1 = gv.batch_counts()
+    assert (cap1, rep1) == (cap0, rep0 + 1)
+    del ix1
+    X2 = X[: c.n // 2].contiguous()                                   # a different index
+    ix2 = gv.encode(md, X2, "bf16", copy_X=True)
+    out2 = gv.search_batched([md], [ix2], [Q], k, kappa, out=out)
+    torch.cuda.synchronize()
+    cap2, _ = gv.batch_counts()
+    assert cap2 == cap1 + 1
+    ids, sc = gv.search(md, ix2, Q, k, kappa)
+    torch.cuda.synchronize()
+    assert torch.equal(out2[0][0], ids) and torch.equal(out2[0][1], sc)
+    gv.batch_release()
+
+
 def test_batched_errors(gv, collections):
     models = [b[1] for b in collections]
     indexes = [b[2] for b in collections]

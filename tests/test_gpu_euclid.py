@@ -7,7 +7,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import problem
+from helpers import check_final_topk, check_topk_sets, exact_scores, problem, reduced_score_tolerance
 from oracle import gleanvec as G
 
 pytestmark = pytest.mark.gpu
@@ -68,18 +68,31 @@ def test_euclidean_search(gv, fmt):
     X = (X * rng.uniform(0.5, 2.0, (X.shape[0], 1))).astype(np.float32)  # unnormalised rows
     d = 49 if fmt == "fp32" else 24
     om = G.fit(G.augment_database(X), G.augment_queries(QL), d, 4, seed=3)
-    oi = G.encode(om.mu, om.B, G.augment_database(X), fmt)
     kappa, k = 64, 10
-    out = G.search(oi, om.A, G.augment_queries(Q), k, kappa)
     model = gv.model_import(om.mu, om.A, om.B)
     Xa = gv.augment(dev(X), "database")
     Qa = gv.augment(dev(Q), "query")
     idx = gv.encode(model, Xa, fmt)
     ids, sc = gv.search(model, idx, Qa, k, kappa)
+    _, t, qhat = gv.project(model, fmt, Qa, want_qc=False)
+    cid, csc = gv.score_topk(idx, qhat, t, kappa)
+    rid, rsc = gv.rerank(idx, Qa, cid, k)
     torch.cuda.synchronize()
-    ids = ids.cpu().numpy()
-    same = np.mean([set(a.tolist()) == set(b.tolist()) for a, b in zip(ids, out["ids"])])
-    assert same >= 0.9, same
+    assert torch.equal(ids, rid) and torch.equal(sc, rsc)
+    # the oracle searches the same augmented vectors (the augmentation itself is
+    # checked against the oracle's above, to one ulp of the appended value)
+    Xa_h, Qa_h = Xa.cpu().numpy(), Qa.cpu().numpy()
+    oi = G.encode(om.mu, om.B, Xa_h, fmt)
+    out = G.search(oi, om.A, Qa_h, k, kappa)
+    ids = ids.cpu().numpy(); cid = cid.cpu().numpy(); csc = csc.cpu().numpy()
+    tol = reduced_score_tolerance(out, oi, idx.d_pad)
+    n = X.shape[0]
+    for qi in range(Q.shape[0]):
+        by_id = np.empty(n); by_id[oi.ids] = out["scores"][qi]
+        tol_id = np.empty(n); tol_id[oi.ids] = tol[qi]
+        check_topk_sets(cid[qi], csc[qi], by_id, tol_id, kappa, f"q{qi}")
+        ex, tl = exact_scores(Xa_h, Qa_h[qi], cid[qi])
+        check_final_topk(ids[qi], cid[qi], ex, tl, k, f"q{qi}")
     if fmt == "fp32":
         dist = cdist(Q.astype(np.float64), X.astype(np.float64), "sqeuclidean")
         checked = 0

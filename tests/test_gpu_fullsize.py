@@ -4,14 +4,16 @@ data, batch and launch shapes bench.py times).  The oracle fits its own model on
 a subsample of the learn rows; the GPU imports that model, encodes all 10M rows
 and searches the whole batch; sampled queries are then checked one by one
 against the oracle's encode and search of the same rows: stored bits on sampled
-rows, top-kappa sets and scores (within the derived tolerance), final top-10."""
+rows, top-kappa sets and scores (within the derived tolerance), and the final
+top-10 as the rerank of the GPU's own candidates -- every difference from the
+oracle proven a near tie."""
 import sys
 
 import numpy as np
 import pytest
 
 import synth
-from helpers import check_topk_sets, decode_stored, reduced_score_tolerance
+from helpers import check_final_topk, check_topk_sets, decode_stored, exact_scores, reduced_score_tolerance
 from oracle import gleanvec as G
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -50,7 +52,11 @@ def test_full_size_sampled_queries():
     _, t, qhat = gv.project(model, fmt, Qd, want_qc=False)
     cid, csc = gv.score_topk(idx, qhat, t, wl.kappa)
     ids, sc = gv.search(model, idx, Qd, k, wl.kappa)
+    rid, rsc = gv.rerank(idx, Qd, cid, k)
     torch.cuda.synchronize()
+    # the search is the composition of its stages, bit for bit
+    assert torch.equal(ids, rid) and torch.equal(sc, rsc)
+    del rid, rsc
     cid = cid.cpu().numpy(); csc = csc.cpu().numpy(); ids = ids.cpu().numpy(); sc = sc.cpu().numpy()
     ex = idx.export()
     del idx, Xd
@@ -69,18 +75,19 @@ def test_full_size_sampled_queries():
         assert (got == oi.xq[pos]).mean() > 0.9999
     del ex
 
-    sample = [0, 1, 1000, 2047, 3071, 4095]
-    _say("[fullsize] oracle search of the sampled queries")
-    out = G.search(oi, om.A, Q[sample], k, wl.kappa)
-    tol = reduced_score_tolerance(out, oi, 160)
-    flips = 0
+    # 32 sampled queries: the first and last of the batch, the rest seeded
+    sample = sorted({0, m - 1, *np.random.default_rng(11).choice(m, 30, replace=False).tolist()})
+    _say(f"[fullsize] oracle S1-S3 of {len(sample)} sampled queries")
+    qc, t, qh = G.project_queries(om.A, Q[sample], fmt)
+    S = G.reduced_scores(oi, t, qh)
+    tol = reduced_score_tolerance({"qh": qh, "t": t, "scores": S}, oi, 160)
+    near = 0
     for j, qi in enumerate(sample):
-        by_id = np.empty(wl.n); by_id[oi.ids] = out["scores"][j]
+        by_id = np.empty(wl.n); by_id[oi.ids] = S[j]
         tol_id = np.empty(wl.n); tol_id[oi.ids] = tol[j]
-        flips += check_topk_sets(cid[qi], csc[qi], by_id, tol_id, wl.kappa, f"q{qi}")
-        exact = X[ids[qi]].astype(np.float64) @ Q[qi].astype(np.float64)
-        assert np.allclose(sc[qi], exact.astype(np.float32), rtol=2 ** -22, atol=0)
-        if ids[qi].tolist() != out["ids"][j].tolist():
-            flips += 1
-    assert flips <= 1
-    _say(f"[fullsize] {len(sample)} sampled queries agree ({flips} near-tie differences)")
+        near += check_topk_sets(cid[qi], csc[qi], by_id, tol_id, wl.kappa, f"q{qi}")
+        ex, tl = exact_scores(X, Q[qi], cid[qi])
+        near += check_final_topk(ids[qi], cid[qi], ex, tl, k, f"q{qi}")
+        exi, _ = exact_scores(X, Q[qi], ids[qi])
+        assert np.allclose(sc[qi], exi.astype(np.float32), rtol=2 ** -23, atol=0)
+    _say(f"[fullsize] {len(sample)} sampled queries verified ({near} proven near-tie differences)")

@@ -68,6 +68,26 @@ def test_host_eigensolver_repeated_and_indefinite():
     assert lam.tolist() == [5.0, 3.0, 1.0]
 
 
+def test_host_eigensolver_reports_nonconvergence():
+    """A step budget too small to deflate every off-diagonal entry is reported as
+    GV_ENOCONV (the fit then fails instead of returning unconverged projections);
+    the default budget converges on the same matrix."""
+    import paper_2410_22347_amd as gv
+    rng = np.random.default_rng(9)
+    M = rng.standard_normal((48, 48))
+    A = M @ M.T
+    gv.eig_step_limit(3)
+    try:
+        with pytest.raises(gv.GleanVecError) as e:
+            gv.host_eigh(A)
+        assert e.value.status == -7
+    finally:
+        gv.eig_step_limit(0)
+    lam, Vt = gv.host_eigh(A)
+    assert np.allclose(A @ Vt.T, Vt.T * lam, atol=1e-10 * lam[0])
+    assert gv._lib.gv_eig_step_limit(-1) == -1
+
+
 def test_host_argument_errors():
     import paper_2410_22347_amd as gv
     lib = gv._lib
@@ -115,3 +135,81 @@ def test_loss_argument_errors():
     assert lib.gv_moments(p, 10, 0, None, 1, p, None) == -1
     assert lib.gv_moments(p, 10, 8, None, 1, None, None) == -1
     assert lib.gv_tags(None, p, 10, p, None) == -4
+
+
+class _ScanLevel(ctypes.Structure):
+    _fields_ = [("stride", ctypes.c_int64), ("rows_per_level", ctypes.c_int64), ("query_blocks", ctypes.c_int64),
+                ("dense", ctypes.c_int32), ("ranges", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("queries_per_wave", ctypes.c_int32), ("shared", ctypes.c_int32), ("xcd_map", ctypes.c_int32),
+                ("tile_ring", ctypes.c_int32), ("workgroups_per_cu", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("staging", ctypes.c_int32), ("list_cap", ctypes.c_int32),
+                ("list_limit", ctypes.c_int32)]
+
+
+def _plan(lib, n, n_pad, C, fmt, d, ds, m, kappa):
+    lv = (_ScanLevel * 8)()
+    nl, keys, ws = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    st = lib.gv_scan_plan(n, n_pad, C, fmt, d, ds, m, kappa, ctypes.cast(lv, ctypes.c_void_p), 8,
+                          ctypes.byref(nl), ctypes.byref(keys), ctypes.byref(ws))
+    return st, [lv[i] for i in range(nl.value)], keys.value, ws.value
+
+
+def test_scan_plan_invariants():
+    """The launch plans of S2/S3 over a grid of batch sizes, database sizes, cluster
+    counts, kappa, reduced lengths, formats and tuning overrides keep the invariants
+    the kernels rely on (two GPU faults of the scan came from launches that broke
+    them: candidate scratch sized without a cascade, and compaction staging smaller
+    than a list):
+      * the scratch holds m x R x cap list slots for every filtering level, fewer
+        than 2^32 of them;
+      * a list checked every U tiles, compacted above list_limit, never outgrows
+        its slots or the wavefront's LDS staging: list_limit + 32 (U + 1) <= min(cap, staging);
+      * a compaction to the kappa best leaves room: list_limit > kappa;
+      * the grid covers every (query block, range) work item exactly;
+      * the cascade's dense sample comes first, the full scan last, strides nested."""
+    import paper_2410_22347_amd as gv
+    lib = gv._lib
+    checked = refused = 0
+    tunings = [(0, 0, 0), (24, 0, 0), (1, 0, 0), (4, 0, 640), (0, 64, 0), (0, 128, 0), (0, 32, 1024)]
+    for splits, qpw, cap in tunings:
+        assert lib.gv_search_tuning(splits, qpw, cap) == 0
+        try:
+            for n in (40, 5_000, 300_000, 10_000_000, 60_000_000):
+                for C in (1, 8, 32, 255):
+                    n_pad = (n + 31 * C) // 32 * 32   # every segment padded: the most tiles
+                    for d in (16, 40, 160, 256):
+                        for fmt in (0, 1, 2, 3):
+                            for m in (1, 33, 64, 65, 600, 4096, 20_000):
+                                for kappa in (1, 50, 200, 256, 800, 1024):
+                                    if kappa > n:
+                                        continue
+                                    st, lv, keys, ws = _plan(lib, n, n_pad, C, fmt, d, 0, m, kappa)
+                                    if st != 0:
+                                        assert st in (-6, -1), st
+                                        refused += 1
+                                        continue
+                                    checked += 1
+                                    assert lv[-1].stride == 1 and not lv[-1].dense
+                                    for a, b in zip(lv[:-1], lv[1:]):
+                                        assert a.stride % b.stride == 0 and a.stride > b.stride
+                                    assert all(not x.dense for x in lv[1:])
+                                    assert keys < 2 ** 32
+                                    for x in lv:
+                                        nb = x.queries_per_wave // 32
+                                        assert x.query_blocks == -(-m // x.queries_per_wave)
+                                        if x.shared:
+                                            assert x.ranges % 4 == 0 and x.grid == x.query_blocks * x.ranges // 4
+                                        else:
+                                            assert x.grid == -(-x.query_blocks // 4) * x.ranges
+                                            assert not x.xcd_map or x.ranges % 8 == 0
+                                        assert 1 <= x.ranges <= 4096
+                                        if x.dense:
+                                            continue
+                                        assert keys >= m * x.ranges * x.list_cap
+                                        assert x.list_limit + 32 * (x.check_every + 1) <= min(x.list_cap, x.staging)
+                                        assert x.list_limit > kappa
+                                        assert nb in (1, 2, 4)
+                                    assert ws >= 8 * keys
+        finally:
+            lib.gv_search_tuning(0, 0, 0)
+    assert checked > 10_000 and refused < checked
