@@ -256,6 +256,27 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
                     int32_t k, int32_t kappa, int32_t* out_ids, float* out_scores, void* stream);
 
 /*
+ * gv_search_noalloc -- gv_search for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, stages and results as gv_search (bit for bit),
+ * but the search scratch lives in a fixed array of the library, one per device,
+ * of gv_search_noalloc_capacity() bytes (64 MiB): the call makes no device
+ * allocation and no allocating library call (and records no profiling events).
+ * The index must keep its full-dimension vectors (copy_X 0 or 1).
+ * Every call on a device uses that device's one array: calls that overlap on
+ * one device (other threads, or other streams not ordered with this one) race
+ * and give undefined results; order them.  A search whose scratch exceeds the
+ * array (large batches: the candidate lists take m x ranges x 2048 x 8 bytes)
+ * returns GV_EINVAL and names the bytes it needs.
+ * Errors: as gv_search; GV_EINVAL also for a search larger than the array.
+ */
+gv_status gv_search_noalloc(const gv_model* model, const gv_index* index, const float* Q, int64_t m,
+                            int32_t k, int32_t kappa, int32_t* out_ids, float* out_scores, void* stream);
+
+/* Bytes of the per-device scratch array of gv_search_noalloc. */
+int64_t gv_search_noalloc_capacity(void);
+
+/*
  * gv_search_batched -- Algorithm 1 for n_coll independent collections (each
  * its own model and index, query batch and outputs), as one graph launch: every
  * collection's S1-S4 sequence is captured as a branch of one HIP graph whose

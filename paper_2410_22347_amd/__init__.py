@@ -32,6 +32,7 @@ EXPORTED = [
     "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored", "gv_augment",
     "gv_moments_update", "gv_fit_from_stats", "gv_batch_counts", "gv_eig_step_limit",
     "gv_model_save", "gv_model_load", "gv_model_file_info", "gv_model_sphering", "gv_scan_plan",
+    "gv_search_noalloc", "gv_search_noalloc_capacity",
 ]
 
 
@@ -77,6 +78,8 @@ _sig("gv_index_shape", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.
 _sig("gv_index_export", [_vp, _vp, _vp, _vp, _vp, _vp])
 _sig("gv_index_destroy", [_vp], None)
 _sig("gv_search", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
+_sig("gv_search_noalloc", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
+_sig("gv_search_noalloc_capacity", [], _i64)
 _sig("gv_project", [_vp, ctypes.c_int, _vp, _i64, _vp, _vp, _vp, _vp])
 _sig("gv_score_topk", [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp])
 _sig("gv_rerank", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
@@ -266,6 +269,22 @@ def search(model: Model, index: Index, Q, k: int, kappa: int, with_scores: bool 
     sc = torch.empty((m, k), dtype=torch.float32, device=Q.device) if with_scores else None
     _check(_lib.gv_search(model._h, index._h, _ptr(Q), m, k, kappa, _ptr(ids), _ptr(sc), _stream()), "gv_search")
     return ids, sc
+
+
+def search_noalloc_into(model: Model, index: Index, Q, k: int, kappa: int, out_ids, out_scores=None):
+    """gv_search_noalloc: the search into caller-given outputs, with no device
+    allocation inside the library (its scratch is a fixed per-device array)."""
+    _dev_f32(Q)
+    m = Q.shape[0]
+    if tuple(out_ids.shape) != (m, k) or (out_scores is not None and tuple(out_scores.shape) != (m, k)):
+        raise ValueError("outputs must be m x k")
+    _check(_lib.gv_search_noalloc(model._h, index._h, _ptr(Q), m, k, kappa, _ptr(out_ids), _ptr(out_scores),
+                                  _stream()), "gv_search_noalloc")
+    return out_ids, out_scores
+
+
+def search_noalloc_capacity() -> int:
+    return int(_lib.gv_search_noalloc_capacity())
 
 
 def augment(V, kind: str):

@@ -21,6 +21,11 @@ void clear_error() { g_err.clear(); }
 int tuned_splits() { return g_splits; }
 int tuned_qpw() { return g_qpw; }
 int tuned_cap() { return g_cap; }
+void set_tuning(int splits, int qpw, int cap) {
+  g_splits = splits;
+  g_qpw = qpw;
+  g_cap = cap;
+}
 
 namespace {
 struct ProfRec {
@@ -35,9 +40,12 @@ bool g_prof_on = false;
 
 bool profiling() { return g_prof_on; }
 
-// set while gv_search_batched captures a graph: no profiling events then
+// set while gv_search_batched captures a graph, or while a call that must not
+// allocate runs: no profiling events then
 static thread_local bool g_capturing = false;
-bool capturing_batch() { return g_capturing; }
+static thread_local bool g_no_events = false;
+bool capturing_batch() { return g_capturing || g_no_events; }
+void suppress_profile_events(bool on) { g_no_events = on; }
 
 void profile_mark(hipStream_t st, int kind, bool begin) {
   if (!g_prof_on || capturing_batch()) return;
@@ -381,13 +389,19 @@ void gv_index_destroy(gv_index* x) {
   delete x;
 }
 
-static gv_status check_search_args(const gv_index* idx, int64_t m, int32_t k, int32_t kappa) {
+}  // extern "C"
+
+namespace gv {
+gv_status check_search_args(const gv_index* idx, int64_t m, int32_t k, int32_t kappa) {
   GV_REQUIRE(m >= 0, "search: m < 0");
   GV_REQUIRE(kappa >= 1 && kappa <= kMaxKappa, "search: need 1 <= kappa <= 1024");
   GV_REQUIRE(k >= 1 && k <= kappa, "search: need 1 <= k <= kappa");
   GV_REQUIRE(kappa <= idx->n, "search: need kappa <= n");
   return GV_OK;
 }
+}  // namespace gv
+
+extern "C" {
 
 gv_status gv_project(const gv_model* model, gv_format fmt, const float* Q, int64_t m, float* qc, float* t, void* qhat,
                      void* stream) {

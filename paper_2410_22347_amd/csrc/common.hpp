@@ -253,6 +253,7 @@ void keep_pool(int device);
 // one search's scratch, carved from a single workspace (byte offsets)
 struct SearchPlan {
   size_t off_t = 0, off_qc = 0, off_qhat = 0, off_cand = 0, off_csc = 0, off_scan = 0, bytes = 0;
+  size_t scan_bytes = 0;  // scratch of S2/S3 within the workspace (search_run re-plans and checks it)
   int d_search = 0;     // leading coordinates scanned
   bool stored = false;  // rerank from the stored vectors instead of the full-dimension X
 };
@@ -309,9 +310,17 @@ void set_eig_step_limit(long max_steps);
 int tuned_splits();
 int tuned_qpw();
 int tuned_cap();
+// the calling thread's launch overrides (as gv_search_tuning, unchecked)
+void set_tuning(int splits, int qpw, int cap);
+// smallest candidate-list capacity the scan accepts for kappa
+int min_list_cap(int kappa);
 
 // benchmark hooks: events around scoring (kind 0) and merge (kind 1) launches
 // (off while a batched search is being captured into a graph)
 bool profiling();
 void profile_mark(hipStream_t st, int kind, bool begin);
+// no profiling events (which create HIP events) on this thread while on
+void suppress_profile_events(bool on);
+// argument rules shared by the search entry points
+gv_status check_search_args(const gv_index* idx, int64_t m, int32_t k, int32_t kappa);
 }  // namespace gv

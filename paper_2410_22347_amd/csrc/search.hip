@@ -587,6 +587,7 @@ gv_status search_plan(const gv_model* model, const gv_index* idx, int64_t m, int
   sp->off_cand = o; o = align256(o + sizeof(int32_t) * m * kappa);
   sp->off_csc = o;  o = align256(o + sizeof(float) * m * kappa);
   sp->off_scan = o; o = align256(o + p.bytes);
+  sp->scan_bytes = p.bytes;
   sp->bytes = std::max<size_t>(o, 256);
   (void)model;
   return GV_OK;
@@ -598,6 +599,10 @@ gv_status search_run(const gv_model* model, const gv_index* idx, const float* Q,
   uint8_t* ws = (uint8_t*)workspace;
   ScanPlan p;
   GV_TRY(plan_scan(idx, m, kappa, &p, sp.d_search));
+  if (p.bytes > sp.scan_bytes) {  // the workspace was sized for another plan (tuning changed in between)
+    set_error("internal: the search plan changed after its workspace was sized");
+    return GV_EDEVICE;
+  }
   float* t = (float*)(ws + sp.off_t);
   float* qc = (float*)(ws + sp.off_qc);
   void* qhat = ws + sp.off_qhat;
