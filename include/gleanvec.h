@@ -209,14 +209,16 @@ void gv_model_destroy(gv_model* model);
 gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format fmt,
                     int32_t copy_X, void* stream, gv_index** out);
 
-/* Shape of an index: rows, clusters, reduced dim, padded row length (see gv_padded_dim), format. */
+/* Shape of an index: id space n (rows encoded, plus rows inserted by re-projections), clusters,
+ * reduced dim, padded row length (see gv_padded_dim), format. */
 gv_status gv_index_shape(const gv_index* index, int64_t* n, int32_t* C, int32_t* d,
                          int32_t* d_pad, int32_t* fmt);
 
 /*
  * gv_index_export -- host copies of the index (any pointer may be NULL):
- * tags (n, uint8, original order), offsets (C + 1, grouped segment starts),
- * ids (n, int32, original id of each grouped position), xlow (n x d_pad
+ * tags (n, uint8, original order, 255 for removed ids), offsets (C + 1, grouped
+ * segment starts), ids (rows, int32, original id of each grouped position,
+ * rows = gv_index_rows), xlow (rows x d_pad
  * elements of the storage format, raw bits, grouped order, zero padded;
  * d_pad = gv_padded_dim(d)),
  * scale (C, FP32 power-of-two s_c).
@@ -225,6 +227,35 @@ gv_status gv_index_export(const gv_index* index, uint8_t* tags, int64_t* offsets
                           void* xlow, float* scale);
 
 void gv_index_destroy(gv_index* index);
+
+/*
+ * gv_index_reproject -- streaming update of an index without the database
+ * (Section 3, streaming vector search): the stored vectors y = P_c W x of `in`
+ * are carried to the refitted projections as
+ *     y' = P'_c W' (P_c W)^-1 y = B'_c A_c^T y
+ * (A_c, B_c of old_model, B'_c of new_model; A_c^T is the inverse of B_c when
+ * d = D and K_Q has full rank), vectors inserted since are encoded as
+ * y' = B'_c x, and removed ones are dropped.  Requires d = D for both models and
+ * the index (flexible storage of all coordinates, Section 3.3) and identical
+ * landmarks (a refit from kept landmarks, gv_fit_from_stats), so every kept
+ * vector keeps its cluster.
+ * keep   device uint8 per id of `in` (nonzero: kept), or NULL to keep all.
+ * X_new  device n_new x D FP32 inserted vectors (ids in.n .. in.n + n_new - 1),
+ *        NULL when n_new == 0.
+ * fmt    storage format of the new index (per-cluster scales recomputed).
+ * out    a new index over the id space [0, in.n + n_new) that keeps no
+ *        full-dimension vectors (search it with gv_search_flex and
+ *        GV_RERANK_STORED); removed ids have no stored vector (tag 255).
+ * Each y' is fl32 of an FP64 product of the exact stored values.
+ * Errors: GV_EINVAL (shapes, d < D, other landmarks, nothing left),
+ * GV_ENOTFIT, GV_ENONFINITE, GV_ENOMEM, GV_EDEVICE.
+ */
+gv_status gv_index_reproject(const gv_model* old_model, const gv_model* new_model, const gv_index* in,
+                             const uint8_t* keep, const float* X_new, int64_t n_new, gv_format fmt,
+                             void* stream, gv_index** out);
+
+/* Number of vectors an index stores (its id space minus removed ids). */
+gv_status gv_index_rows(const gv_index* index, int64_t* rows);
 
 /* ------------------------------------------------------------------ search */
 

@@ -278,6 +278,54 @@ def fit_from_stats(mu: np.ndarray, KQ_sum: np.ndarray, m_q: float, KX: np.ndarra
                                   np.asarray(KX, np.float64), counts, d)
 
 
+def reproject_index(index: "Index", mu: np.ndarray, A_old: np.ndarray, B_new: np.ndarray, fmt: str,
+                    X_new: np.ndarray | None = None, keep: np.ndarray | None = None) -> "Index":
+    """Streaming re-projection of stored vectors (Section 3, streaming vector
+    search).  The index stores y = P_c W x with every coordinate (d = D, the
+    flexible storage of Section 3.3).  After a refit, the kept vectors become
+    P'_c W' (P_c W)^-1 y, where (P_c W)^-1 = W^-1 P_c^T is A_c^T = (P_c W+)^T
+    (P_c orthogonal, K_Q of full rank); inserted vectors x become P'_c W' x =
+    B'_c x; removed ones are dropped.  The landmarks mu are unchanged, so kept
+    vectors keep their tag.  Stored values y are s_c x^ (exact); each new value
+    is the float64 product rounded once to FP32, then scaled per cluster and
+    rounded to fmt as in encode.  The result keeps no full-dimension vectors;
+    removed ids get tag 255."""
+    C = mu.shape[0]
+    n_old = index.tags.shape[0]
+    X_new = np.zeros((0, A_old.shape[2]), np.float32) if X_new is None else np.asarray(X_new, np.float32)
+    tags = np.concatenate([np.asarray(index.tags, np.int64), assign(np.asarray(X_new, np.float64), mu)])
+    if keep is not None:
+        tags[:n_old][~np.asarray(keep, bool)] = 255
+    present = np.nonzero(tags < C)[0]
+    ids = present[np.argsort(tags[present], kind="stable")].astype(np.int64)   # by (tag, id)
+    counts = np.bincount(tags[present], minlength=C)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    pos_old = np.empty(n_old, np.int64)
+    pos_old[index.ids] = np.arange(index.ids.shape[0])
+    d = B_new.shape[1]
+    v = np.empty((ids.shape[0], d))
+    xq = np.empty((ids.shape[0], d))
+    scale = np.ones(C)
+    for c in range(C):
+        rows = ids[offsets[c]:offsets[c + 1]]
+        T = np.asarray(B_new[c], np.float64) @ np.asarray(A_old[c], np.float64).T
+        vc = np.empty((rows.shape[0], d))
+        for r, i in enumerate(rows):
+            if i < n_old:
+                y = index.xq[pos_old[i]] * index.scale[c]          # the stored vector, exactly
+                vc[r] = T @ y
+            else:
+                vc[r] = np.asarray(B_new[c], np.float64) @ X_new[i - n_old].astype(np.float64)
+        vc = formats.round_to("fp32", vc)
+        v[offsets[c]:offsets[c + 1]] = vc
+        amax = np.max(np.abs(vc)) if vc.size else 0.0
+        s = float(formats.pow2_scale(fmt, amax))
+        scale[c] = s
+        xq[offsets[c]:offsets[c + 1]] = formats.round_to(fmt, vc / s)
+    out_tags = np.where(tags < C, tags, 255).astype(np.int64)
+    return Index(fmt, out_tags, offsets, ids, v, xq, scale, None)
+
+
 # ============================================================================ encode
 @dataclasses.dataclass
 class Index:
@@ -288,7 +336,7 @@ class Index:
     v: np.ndarray         # n x d, fl32(B_c x) in grouped order (float64 holding FP32 values)
     xq: np.ndarray        # n x d, stored values x^ (float64 holding fmt values), grouped order
     scale: np.ndarray     # C, per-cluster power-of-two scale s_c
-    X: np.ndarray         # n x D original vectors (FP32), original order
+    X: np.ndarray | None  # n x D original vectors (FP32), original order; None when not kept
 
 
 def encode(model_mu: np.ndarray, B: np.ndarray, X: np.ndarray, fmt: str) -> Index:
@@ -439,7 +487,7 @@ def rerank_stored(index: Index, qc: np.ndarray, q: int, cand_ids: np.ndarray):
     """Rerank of one query's candidates from the stored vectors (Section 3.3):
     <A_c q, x'_i> = sum_j q_{c,j} * (s_c x^_{i,j}) over every stored coordinate,
     float64, c the candidate's cluster.  Returns the scores of cand_ids."""
-    pos_of = np.empty(index.ids.shape[0], np.int64)
+    pos_of = np.full(index.tags.shape[0], -1, np.int64)   # id -> stored row (ids may have gaps)
     pos_of[index.ids] = np.arange(index.ids.shape[0])
     out = np.empty(cand_ids.shape[0])
     for r, i in enumerate(cand_ids):

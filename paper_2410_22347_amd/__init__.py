@@ -32,7 +32,7 @@ EXPORTED = [
     "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored", "gv_augment",
     "gv_moments_update", "gv_fit_from_stats", "gv_batch_counts", "gv_eig_step_limit",
     "gv_model_save", "gv_model_load", "gv_model_file_info", "gv_model_sphering", "gv_scan_plan",
-    "gv_search_noalloc", "gv_search_noalloc_capacity",
+    "gv_search_noalloc", "gv_search_noalloc_capacity", "gv_index_reproject", "gv_index_rows",
 ]
 
 
@@ -77,6 +77,8 @@ _sig("gv_index_shape", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.
                         ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
 _sig("gv_index_export", [_vp, _vp, _vp, _vp, _vp, _vp])
 _sig("gv_index_destroy", [_vp], None)
+_sig("gv_index_reproject", [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.c_int, _vp, ctypes.POINTER(_vp)])
+_sig("gv_index_rows", [_vp, ctypes.POINTER(_i64)])
 _sig("gv_search", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_search_noalloc", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_search_noalloc_capacity", [], _i64)
@@ -205,6 +207,9 @@ class Index:
         _check(_lib.gv_index_shape(self._h, ctypes.byref(n), ctypes.byref(C), ctypes.byref(d), ctypes.byref(dp),
                                    ctypes.byref(f)), "gv_index_shape")
         self.n, self.C, self.d, self.d_pad, self.fmt = n.value, C.value, d.value, dp.value, f.value
+        rows = _i64()
+        _check(_lib.gv_index_rows(self._h, ctypes.byref(rows)), "gv_index_rows")
+        self.rows = rows.value   # stored vectors (n minus removed ids)
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -216,8 +221,8 @@ class Index:
         dt = {4: np.uint32, 2: np.uint16, 1: np.uint8}[eb]
         tags = np.empty(self.n, np.uint8)
         off = np.empty(self.C + 1, np.int64)
-        ids = np.empty(self.n, np.int32)
-        xlow = np.empty((self.n, self.d_pad), dt)
+        ids = np.empty(self.rows, np.int32)
+        xlow = np.empty((self.rows, self.d_pad), dt)
         scale = np.empty(self.C, np.float32)
         _check(_lib.gv_index_export(self._h, _np_ptr(tags), _np_ptr(off), _np_ptr(ids), _np_ptr(xlow),
                                     _np_ptr(scale)), "gv_index_export")
@@ -269,6 +274,26 @@ def search(model: Model, index: Index, Q, k: int, kappa: int, with_scores: bool 
     sc = torch.empty((m, k), dtype=torch.float32, device=Q.device) if with_scores else None
     _check(_lib.gv_search(model._h, index._h, _ptr(Q), m, k, kappa, _ptr(ids), _ptr(sc), _stream()), "gv_search")
     return ids, sc
+
+
+def index_reproject(old_model: Model, new_model: Model, index: Index, keep=None, X_new=None, fmt=None) -> Index:
+    """gv_index_reproject: the index's stored vectors carried to new_model's
+    projections without X (Section 3, streaming), plus inserted vectors X_new
+    (ids index.n ...), minus the ids whose keep flag (uint8 CUDA tensor, one per
+    id) is zero.  The result keeps no full-dimension vectors."""
+    import torch
+    f = FORMATS[fmt] if isinstance(fmt, str) else (index.fmt if fmt is None else fmt)
+    if keep is not None and not (keep.is_cuda and keep.dtype == torch.uint8 and keep.numel() == index.n
+                                 and keep.is_contiguous()):
+        raise ValueError("keep must be a contiguous uint8 CUDA tensor with one flag per id")
+    n_new = 0
+    if X_new is not None:
+        _dev_f32(X_new)
+        n_new = X_new.shape[0]
+    h = _vp()
+    _check(_lib.gv_index_reproject(old_model._h, new_model._h, index._h, _ptr(keep), _ptr(X_new), n_new, f,
+                                   _stream(), ctypes.byref(h)), "gv_index_reproject")
+    return Index(h)
 
 
 def search_noalloc_into(model: Model, index: Index, Q, k: int, kappa: int, out_ids, out_scores=None):

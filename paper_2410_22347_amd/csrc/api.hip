@@ -296,6 +296,7 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
     x->D = model->D;
     x->fmt = fmt;
     x->n = n;
+    x->n_rows = n;
     x->tags = nullptr;
     x->offsets = nullptr;
     x->seg_end = nullptr;
@@ -333,6 +334,89 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
     *out = x;
     return GV_OK;
   });
+}
+
+gv_status gv_index_reproject(const gv_model* old_model, const gv_model* new_model, const gv_index* in,
+                             const uint8_t* keep, const float* X_new, int64_t n_new, gv_format fmt, void* stream,
+                             gv_index** out) {
+  return guarded([&]() -> gv_status {
+    GV_REQUIRE(out != nullptr, "gv_index_reproject: out is NULL");
+    *out = nullptr;
+    if (!valid(old_model) || !valid(new_model) || !valid(in)) return GV_ENOTFIT;
+    const int C = new_model->C, D = new_model->D;
+    GV_REQUIRE(old_model->C == C && old_model->D == D && in->C == C && in->D == D,
+               "gv_index_reproject: models and index differ in C or D");
+    GV_REQUIRE(old_model->d == D && new_model->d == D && in->d == D,
+               "gv_index_reproject: the models and the index must keep all D coordinates (d = D)");
+    GV_REQUIRE(fmt >= GV_FP32 && fmt <= GV_FP8_E4M3, "gv_index_reproject: unknown format");
+    GV_REQUIRE(n_new >= 0 && (n_new == 0 || X_new != nullptr), "gv_index_reproject: NULL new vectors");
+    GV_REQUIRE(in->n + n_new <= 0x7fffffffLL, "gv_index_reproject: id space beyond 2^31");
+    int dev = 0;
+    GV_HIP(hipGetDevice(&dev));
+    GV_REQUIRE(in->device == dev, "gv_index_reproject: the index lives on another device");
+    {  // the landmarks must be the same: kept vectors keep their clusters
+      std::vector<double> mu0((size_t)C * D), mu1((size_t)C * D);
+      GV_HIP(hipMemcpy(mu0.data(), old_model->mu, sizeof(double) * mu0.size(), hipMemcpyDeviceToHost));
+      GV_HIP(hipMemcpy(mu1.data(), new_model->mu, sizeof(double) * mu1.size(), hipMemcpyDeviceToHost));
+      GV_REQUIRE(std::memcmp(mu0.data(), mu1.data(), sizeof(double) * mu0.size()) == 0,
+                 "gv_index_reproject: the models' landmarks differ (refit with the landmarks kept)");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (n_new > 0) {
+      bool fin = false;
+      GV_TRY(check_finite_f32(X_new, n_new * D, st, &fin));
+      if (!fin) {
+        set_error("gv_index_reproject: NaN or Inf in the new vectors");
+        return GV_ENONFINITE;
+      }
+    }
+    gv_index* x = new gv_index();
+    x->device = dev;
+    x->magic = kIndexMagic;
+    x->gen = next_handle_gen();
+    x->C = C;
+    x->d = D;
+    x->dp = pad_dim(D);
+    x->D = D;
+    x->fmt = fmt;
+    x->n = in->n + n_new;
+    x->n_rows = 0;
+    x->tags = nullptr;
+    x->offsets = nullptr;
+    x->seg_end = nullptr;
+    x->ids = nullptr;
+    x->pos = nullptr;
+    x->xlow = nullptr;
+    x->scale = nullptr;
+    x->X = nullptr;  // no full-dimension vectors: searches rerank from the stored ones
+    x->own_X = false;
+    x->n_pad = 0;
+    auto fail = [&](gv_status s) {
+      gv_index_destroy(x);
+      return s;
+    };
+    if (hipMalloc(&x->tags, std::max<int64_t>(x->n, 1)) != hipSuccess ||
+        hipMalloc(&x->offsets, sizeof(int64_t) * (C + 1)) != hipSuccess ||
+        hipMalloc(&x->seg_end, sizeof(int64_t) * C) != hipSuccess ||
+        hipMalloc(&x->scale, sizeof(float) * C) != hipSuccess) {
+      set_error("gv_index_reproject: device allocation failed");
+      return fail(GV_ENOMEM);
+    }
+    gv_status s = reproject_impl(old_model, new_model, in, keep, X_new, n_new, fmt, st, x);
+    if (s != GV_OK) return fail(s);
+    if (x->n_rows < 1) {
+      set_error("gv_index_reproject: no vectors left");
+      return fail(GV_EINVAL);
+    }
+    *out = x;
+    return GV_OK;
+  });
+}
+
+gv_status gv_index_rows(const gv_index* x, int64_t* rows) {
+  if (!valid(x)) return GV_ENOTFIT;
+  if (rows) *rows = x->n_rows;
+  return GV_OK;
 }
 
 gv_status gv_index_shape(const gv_index* x, int64_t* n, int32_t* C, int32_t* d, int32_t* d_pad, int32_t* fmt) {
@@ -396,7 +480,7 @@ gv_status check_search_args(const gv_index* idx, int64_t m, int32_t k, int32_t k
   GV_REQUIRE(m >= 0, "search: m < 0");
   GV_REQUIRE(kappa >= 1 && kappa <= kMaxKappa, "search: need 1 <= kappa <= 1024");
   GV_REQUIRE(k >= 1 && k <= kappa, "search: need 1 <= k <= kappa");
-  GV_REQUIRE(kappa <= idx->n, "search: need kappa <= n");
+  GV_REQUIRE(kappa <= idx->n_rows, "search: need kappa <= stored vectors");
   return GV_OK;
 }
 }  // namespace gv

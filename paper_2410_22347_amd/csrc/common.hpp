@@ -206,14 +206,15 @@ struct gv_index {
   uint64_t magic;
   uint64_t gen;  // unique per handle in the process (never reused, unlike its address)
   int C, d, dp, D, fmt;
-  int64_t n;       // database rows
+  int64_t n;       // id space: original ids lie in [0, n) (every one stored, unless removed by a re-projection)
+  int64_t n_rows;  // stored vectors (n minus removed ids)
   int64_t n_pad;   // stored rows: every cluster segment padded to a multiple of 32
   int device;
-  uint8_t* tags;     // device n, cluster of each original row
+  uint8_t* tags;     // device n, cluster of each original id (255: removed)
   int64_t* offsets;  // device C+1, padded segment starts (multiples of 32)
   int64_t* seg_end;  // device C, first padding row of each segment (offsets[c] + rows of c)
   int32_t* ids;      // device n_pad, original id of each stored row, -1 for padding
-  int32_t* pos;      // device n, stored row of each original id
+  int32_t* pos;      // device n, stored row of each original id (-1: removed)
   void* xlow;        // device n_pad x dp elements of fmt, matrix-core tiled
   float* scale;      // device C
   const float* X;    // device n x D (owned if own_X), NULL when the index keeps none
@@ -236,6 +237,12 @@ gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, 
                    uint64_t seed, const gv_fit_opts* opts, hipStream_t st, gv_model* model);
 gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt, hipStream_t st,
                       gv_index* index);
+// encode steps shared with the re-projection of stored vectors: grouping of the
+// rows of index->tags (tags >= C absent) and the scaled storage of grouped rows
+gv_status group_rows(int64_t n, int C, int dp, int fmt, hipStream_t st, gv_index* idx, int64_t** ids64_out);
+gv_status quantize_rows(const float* v, int d, int fmt, hipStream_t st, gv_index* idx);
+gv_status reproject_impl(const gv_model* m0, const gv_model* m1, const gv_index* in, const uint8_t* keep,
+                         const float* X_new, int64_t n_new, int fmt, hipStream_t st, gv_index* out);
 gv_status sphere_project(gv_model* model, const double* KX_dev, const std::vector<int64_t>& counts,
                          const double* mu_dev, hipStream_t st);
 gv_status fit_from_stats_impl(const double* mu, const double* KQ, double m_q, const double* KX,

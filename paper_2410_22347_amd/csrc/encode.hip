@@ -49,7 +49,7 @@ __global__ void k_block_hist(const uint8_t* __restrict__ tags, int64_t n, int C,
   const int64_t r0 = (int64_t)blockIdx.x * kBlockRows;
   for (int i = threadIdx.x; i < kBlockRows; i += blockDim.x) {
     int64_t r = r0 + i;
-    if (r < n) atomicAdd(&h[tags[r]], 1);
+    if (r < n && tags[r] < C) atomicAdd(&h[tags[r]], 1);
   }
   __syncthreads();
   for (int c = threadIdx.x; c < C; c += blockDim.x) hist[(int64_t)blockIdx.x * C + c] = h[c];
@@ -68,6 +68,10 @@ __global__ void k_block_scatter(const uint8_t* __restrict__ tags, int64_t n, int
   if (threadIdx.x == 0) {
     const int rows = (int)min<int64_t>(kBlockRows, n - r0);
     for (int i = 0; i < rows; ++i) {
+      if (t[i] >= C) {  // an absent id (removed vector): no stored row
+        pos[r0 + i] = -1;
+        continue;
+      }
       int64_t p = cnt[t[i]]++;
       ids[p] = (int32_t)(r0 + i);
       ids64[p] = r0 + i;
@@ -143,73 +147,67 @@ gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* t
   return GV_OK;
 }
 
-gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt, hipStream_t st, gv_index* idx) {
-  const int C = model->C, d = model->d, D = model->D, dp = pad_dim(d);
-
-  // ------------------------------------------------ tags, FP64 arg-max (Eq. 9)
-  GV_TRY(tags_impl(model, X, n, idx->tags, st));
-
-  // ------------------------------------------------ stable grouping by tag, padded segments
+// Groups the rows 0..n-1 of idx->tags by tag (stable, increasing ids inside a
+// cluster; tags >= C are absent rows), pads every segment to whole tiles, and
+// allocates and fills offsets, seg_end, ids, pos and the storage xlow of the
+// index (dp padded columns of format fmt).  *ids64: device n_pad original ids
+// of the stored rows (-1 padding), to be freed by the caller with hipFreeAsync.
+gv_status group_rows(int64_t n, int C, int dp, int fmt, hipStream_t st, gv_index* idx, int64_t** ids64_out) {
   const int64_t nb = (n + kBlockRows - 1) / kBlockRows;
   int64_t* ids64 = nullptr;
-  {
-    int32_t* hist = nullptr;
-    int64_t* base = nullptr;
-    GV_HIP(hipMallocAsync((void**)&hist, sizeof(int32_t) * nb * C, st));
-    GV_HIP(hipMallocAsync((void**)&base, sizeof(int64_t) * nb * C, st));
-    hipLaunchKernelGGL(k_block_hist, dim3((unsigned)nb), dim3(256), 0, st, idx->tags, n, C, hist);
-    GV_HIP(hipGetLastError());
-    std::vector<int32_t> h_hist((size_t)nb * C);
-    GV_HIP(hipMemcpyAsync(h_hist.data(), hist, sizeof(int32_t) * nb * C, hipMemcpyDeviceToHost, st));
-    GV_HIP(hipStreamSynchronize(st));
-    std::vector<int64_t> h_base((size_t)nb * C);
-    idx->h_offsets.assign(C + 1, 0);
-    idx->h_counts.assign(C, 0);
-    int64_t run = 0;
-    for (int c = 0; c < C; ++c) {
-      idx->h_offsets[c] = run;
-      int64_t cnt = 0;
-      for (int64_t b = 0; b < nb; ++b) {
-        h_base[(size_t)c * nb + b] = run + cnt;
-        cnt += h_hist[(size_t)b * C + c];
-      }
-      idx->h_counts[c] = cnt;
-      run += (cnt + kTileRows - 1) / kTileRows * kTileRows;
-    }
-    idx->h_offsets[C] = run;
-    idx->n_pad = run;
-    GV_HIP(hipMalloc((void**)&idx->ids, sizeof(int32_t) * std::max<int64_t>(run, 1)));
-    GV_HIP(hipMalloc((void**)&idx->pos, sizeof(int32_t) * n));
-    GV_HIP(hipMalloc(&idx->xlow, (size_t)std::max<int64_t>(run, 1) * dp * fmt_bytes(fmt)));
-    GV_HIP(hipMallocAsync((void**)&ids64, sizeof(int64_t) * std::max<int64_t>(run, 1), st));
-    GV_HIP(hipMemsetAsync(idx->ids, 0xFF, sizeof(int32_t) * run, st));  // -1: padding
-    GV_HIP(hipMemcpyAsync(base, h_base.data(), sizeof(int64_t) * nb * C, hipMemcpyHostToDevice, st));
-    GV_HIP(hipMemcpyAsync(idx->offsets, idx->h_offsets.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, st));
-    std::vector<int64_t> h_end(C);
-    for (int c = 0; c < C; ++c) h_end[c] = idx->h_offsets[c] + idx->h_counts[c];
-    GV_HIP(hipMemcpyAsync(idx->seg_end, h_end.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nb), dim3(64), 0, st, idx->tags, n, C, base, nb, idx->ids,
-                       ids64, idx->pos);
-    GV_HIP(hipGetLastError());
-    GV_HIP(hipFreeAsync(hist, st));
-    GV_HIP(hipFreeAsync(base, st));
-    GV_HIP(hipStreamSynchronize(st));  // the host staging vectors end with this block
-  }
-  const int64_t n_pad = idx->n_pad;
-
-  // ------------------------------------------------ x_low = fl32(B_c x), FP64 accumulation (Eq. 10)
-  float* v = nullptr;
-  GV_HIP(hipMallocAsync((void**)&v, sizeof(float) * std::max<int64_t>(n_pad, 1) * d, st));
-  GV_HIP(hipMemsetAsync(v, 0, sizeof(float) * n_pad * d, st));
+  int32_t* hist = nullptr;
+  int64_t* base = nullptr;
+  GV_HIP(hipMallocAsync((void**)&hist, sizeof(int32_t) * nb * C, st));
+  GV_HIP(hipMallocAsync((void**)&base, sizeof(int64_t) * nb * C, st));
+  hipLaunchKernelGGL(k_block_hist, dim3((unsigned)nb), dim3(256), 0, st, idx->tags, n, C, hist);
+  GV_HIP(hipGetLastError());
+  std::vector<int32_t> h_hist((size_t)nb * C);
+  GV_HIP(hipMemcpyAsync(h_hist.data(), hist, sizeof(int32_t) * nb * C, hipMemcpyDeviceToHost, st));
+  GV_HIP(hipStreamSynchronize(st));
+  std::vector<int64_t> h_base((size_t)nb * C);
+  idx->h_offsets.assign(C + 1, 0);
+  idx->h_counts.assign(C, 0);
+  int64_t run = 0, rows = 0;
   for (int c = 0; c < C; ++c) {
-    const int64_t a = idx->h_offsets[c], nc = idx->h_counts[c];
-    if (nc == 0) continue;
-    GemmOperand<float> xo{X, D, ids64 + a, Layout::RowMajor};
-    GemmOperand<double> bo{model->B + (int64_t)c * d * D, D, nullptr, Layout::RowMajor};
-    GV_TRY(gemm_f64<float, double>(nc, d, D, xo, bo, Epi::StoreF32, GemmOut{v + a * d, d, 0, 0, nullptr}, st));
+    idx->h_offsets[c] = run;
+    int64_t cnt = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      h_base[(size_t)c * nb + b] = run + cnt;
+      cnt += h_hist[(size_t)b * C + c];
+    }
+    idx->h_counts[c] = cnt;
+    rows += cnt;
+    run += (cnt + kTileRows - 1) / kTileRows * kTileRows;
   }
+  idx->h_offsets[C] = run;
+  idx->n_pad = run;
+  idx->n_rows = rows;
+  GV_HIP(hipMalloc((void**)&idx->ids, sizeof(int32_t) * std::max<int64_t>(run, 1)));
+  GV_HIP(hipMalloc((void**)&idx->pos, sizeof(int32_t) * std::max<int64_t>(n, 1)));
+  GV_HIP(hipMalloc(&idx->xlow, (size_t)std::max<int64_t>(run, 1) * dp * fmt_bytes(fmt)));
+  GV_HIP(hipMallocAsync((void**)&ids64, sizeof(int64_t) * std::max<int64_t>(run, 1), st));
+  GV_HIP(hipMemsetAsync(idx->ids, 0xFF, sizeof(int32_t) * run, st));   // -1: padding
+  GV_HIP(hipMemsetAsync(ids64, 0xFF, sizeof(int64_t) * run, st));
+  GV_HIP(hipMemcpyAsync(base, h_base.data(), sizeof(int64_t) * nb * C, hipMemcpyHostToDevice, st));
+  GV_HIP(hipMemcpyAsync(idx->offsets, idx->h_offsets.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, st));
+  std::vector<int64_t> h_end(C);
+  for (int c = 0; c < C; ++c) h_end[c] = idx->h_offsets[c] + idx->h_counts[c];
+  GV_HIP(hipMemcpyAsync(idx->seg_end, h_end.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nb), dim3(64), 0, st, idx->tags, n, C, base, nb, idx->ids, ids64,
+                     idx->pos);
+  GV_HIP(hipGetLastError());
+  GV_HIP(hipFreeAsync(hist, st));
+  GV_HIP(hipFreeAsync(base, st));
+  GV_HIP(hipStreamSynchronize(st));  // the host staging vectors end with this block
+  *ids64_out = ids64;
+  return GV_OK;
+}
 
-  // ------------------------------------------------ per-cluster scale and quantisation
+// Per-cluster power-of-two scale from the amax of the grouped FP32 rows v
+// (n_pad x d, padding rows zero) and the rounded storage of every row.
+gv_status quantize_rows(const float* v, int d, int fmt, hipStream_t st, gv_index* idx) {
+  const int C = idx->C, dp = idx->dp;
+  const int64_t n_pad = idx->n_pad;
   uint32_t* amax = nullptr;
   GV_HIP(hipMallocAsync((void**)&amax, sizeof(uint32_t) * C, st));
   GV_HIP(hipMemsetAsync(amax, 0, sizeof(uint32_t) * C, st));
@@ -247,6 +245,35 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
   }
   GV_HIP(hipGetLastError());
   GV_HIP(hipFreeAsync(amax, st));
+  GV_HIP(hipStreamSynchronize(st));
+  return GV_OK;
+}
+
+gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt, hipStream_t st, gv_index* idx) {
+  const int C = model->C, d = model->d, D = model->D, dp = pad_dim(d);
+
+  // ------------------------------------------------ tags, FP64 arg-max (Eq. 9)
+  GV_TRY(tags_impl(model, X, n, idx->tags, st));
+
+  // ------------------------------------------------ stable grouping by tag, padded segments
+  int64_t* ids64 = nullptr;
+  GV_TRY(group_rows(n, C, dp, fmt, st, idx, &ids64));
+  const int64_t n_pad = idx->n_pad;
+
+  // ------------------------------------------------ x_low = fl32(B_c x), FP64 accumulation (Eq. 10)
+  float* v = nullptr;
+  GV_HIP(hipMallocAsync((void**)&v, sizeof(float) * std::max<int64_t>(n_pad, 1) * d, st));
+  GV_HIP(hipMemsetAsync(v, 0, sizeof(float) * n_pad * d, st));
+  for (int c = 0; c < C; ++c) {
+    const int64_t a = idx->h_offsets[c], nc = idx->h_counts[c];
+    if (nc == 0) continue;
+    GemmOperand<float> xo{X, D, ids64 + a, Layout::RowMajor};
+    GemmOperand<double> bo{model->B + (int64_t)c * d * D, D, nullptr, Layout::RowMajor};
+    GV_TRY(gemm_f64<float, double>(nc, d, D, xo, bo, Epi::StoreF32, GemmOut{v + a * d, d, 0, 0, nullptr}, st));
+  }
+
+  // ------------------------------------------------ per-cluster scale and quantisation
+  GV_TRY(quantize_rows(v, d, fmt, st, idx));
   GV_HIP(hipFreeAsync(v, st));
   GV_HIP(hipFreeAsync(ids64, st));
   GV_HIP(hipStreamSynchronize(st));

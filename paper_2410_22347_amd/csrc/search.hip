@@ -446,7 +446,8 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
 }
 
 gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int d_search = 0) {
-  return plan_scan_dims(idx->n, idx->n_pad, idx->C, idx->fmt, idx->dp, d_search > 0 ? d_search : idx->d, m, kappa, p);
+  return plan_scan_dims(idx->n_rows, idx->n_pad, idx->C, idx->fmt, idx->dp, d_search > 0 ? d_search : idx->d, m,
+                        kappa, p);
 }
 
 gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const void* qhat, const float* t, int64_t m,
@@ -736,6 +737,7 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank_stored(
     if (id < 0 || id >= n) continue;  // a missing candidate is skipped
     const int c = tags[id];
     const int64_t p = pos[id];
+    if (c >= C || p < 0) continue;    // a removed id has no stored vector
     const int64_t t = p / kTileRows;
     const int i = (int)(p - t * kTileRows);
     const float* qv = qc + (q * C + c) * (int64_t)dps;

@@ -803,3 +803,64 @@ def test_fit_from_stats_equals_fit_with_kept_landmarks():
     got = G.fit_from_stats(model.mu, KQs, QL.shape[0], KX, np.bincount(tags, minlength=4), 5)
     assert np.allclose(got.A, ref.A, atol=1e-10) and np.allclose(got.B, ref.B, atol=1e-10)
     assert np.array_equal(got.fallback, ref.fallback)
+
+
+# ----------------------------------------------------------------------------- streaming re-projection (Section 3)
+
+def _stream_models(seed=41, D=12, C=3):
+    rng = np.random.default_rng(seed)
+    means = G.normalise_rows(rng.standard_normal((C, D))) * 2
+    X0 = np.concatenate([_lowrank_data(rng, 400, D, mean=means[c]) for c in range(C)]).astype(np.float32)
+    Xn = np.concatenate([_lowrank_data(rng, 60, D, mean=means[c]) for c in range(C)]).astype(np.float32)
+    QL = _lowrank_data(rng, 500, D).astype(np.float32)
+    m0 = G.fit(X0, QL, D, C, seed=3)
+    keep = np.ones(X0.shape[0], bool)
+    keep[rng.choice(X0.shape[0], 90, replace=False)] = False
+    t0 = G.assign(X0.astype(np.float64), m0.mu)
+    tn = G.assign(Xn.astype(np.float64), m0.mu)
+    K = G.update_moments(m0.KX, Xn, tn, +1)
+    K = G.update_moments(K, X0[~keep], t0[~keep], -1)
+    QL2 = _lowrank_data(rng, 300, D).astype(np.float32)
+    KQ = G.second_moment(np.concatenate([QL, QL2]), mean=False)
+    counts = np.bincount(np.concatenate([t0[keep], tn]), minlength=C)
+    m1 = G.fit_from_stats(m0.mu, KQ, QL.shape[0] + QL2.shape[0], K, counts, D)
+    return X0, Xn, keep, m0, m1
+
+
+def test_reproject_equals_fresh_encode_at_full_rank():
+    """With every coordinate stored (d = D) and K_Q of full rank, P'W'(PW)^-1 applied to
+    the stored P W x is P'W'x: the re-projected index equals a fresh encode of the
+    current set with the refitted model, up to the FP32 rounding of the stored values
+    carried through the transform; removed ids are gone, inserted ones take the next
+    ids and the arg-max tag of the kept landmarks."""
+    X0, Xn, keep, m0, m1 = _stream_models()
+    n0, D = X0.shape
+    idx0 = G.encode(m0.mu, m0.B, X0, "fp32")
+    re = G.reproject_index(idx0, m0.mu, m0.A, m1.B, "fp32", X_new=Xn, keep=keep)
+    X_all = np.concatenate([X0, Xn])
+    present = np.concatenate([keep, np.ones(Xn.shape[0], bool)])
+    # fresh encode of the current set, mapped back to the id space
+    cur_ids = np.nonzero(present)[0]
+    fresh = G.encode(m1.mu, m1.B, X_all[cur_ids], "fp32")
+    assert np.all(re.tags[~present] == 255)
+    assert np.array_equal(re.tags[present], fresh.tags)
+    assert np.array_equal(re.ids, cur_ids[fresh.ids])
+    assert np.array_equal(re.offsets, fresh.offsets)
+    err = np.abs(re.v - fresh.v).max(axis=1) / np.linalg.norm(fresh.v, axis=1)
+    assert err.max() < 1e-5, err.max()
+    # kept vectors keep their cluster
+    assert np.array_equal(re.tags[:n0][keep], idx0.tags[keep])
+
+
+def test_reproject_with_the_same_model_keeps_the_stored_values():
+    """With no refit, B_c A_c^T = P W W+ P^T = I (d = D, full rank): every stored value
+    comes back, up to the FP64 rounding of the identity."""
+    X0, Xn, keep, m0, m1 = _stream_models(seed=43)
+    for fmt in ("fp32", "fp16"):
+        idx0 = G.encode(m0.mu, m0.B, X0, fmt)
+        re = G.reproject_index(idx0, m0.mu, m0.A, m0.B, fmt)
+        assert np.array_equal(re.ids, idx0.ids) and np.array_equal(re.offsets, idx0.offsets)
+        y = idx0.xq * idx0.scale[np.repeat(np.arange(idx0.scale.shape[0]), np.diff(idx0.offsets))][:, None]
+        same = re.v == y
+        assert same.mean() > 0.999
+        assert np.all(np.abs(re.v - y) <= np.spacing(np.abs(y).astype(np.float32)).astype(np.float64) + 1e-30)
