@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--cpu-queries", type=int, default=128)
     ap.add_argument("--splits", type=int, default=0, help="override the row ranges per query block (0: automatic)")
     ap.add_argument("--qpw", type=int, default=0, help="override the queries per wavefront (0: automatic)")
+    ap.add_argument("--cap", type=int, default=0, help="override the candidate-list capacity (0: automatic)")
     ap.add_argument("--batched", action="store_true",
                     help="the batched uneven workload instead: 64 collections (n in [1e4, 2e6], D in {256..1024}, "
                          "d = D/4, C in {4, 16, 32}, m log-uniform in [1, 4096], bf16, kappa 100) in one graph launch")
@@ -97,22 +98,23 @@ def recall(found, truth, K=10):
     return float(np.mean([len(set(f[:K].tolist()) & set(g[:K].tolist())) / K for f, g in zip(found, truth)]))
 
 
-def time_search(gv, model, index, Qpool, m, k, kappa, steps, warmup):
+def time_search(gv, model, index, Qpool, m, k, kappa, steps, warmup, fn=None):
     """Wall-clock time of `steps` batches of m queries (rotating through the
     pool), and the average duration of the full scan and of the final select
-    from the library's HIP events."""
+    from the library's HIP events.  fn: the search call (default gv.search)."""
     import torch
+    fn = fn or gv.search
     nb = max(1, Qpool.shape[0] // m)
     batches = [Qpool[(i % nb) * m:(i % nb) * m + m] for i in range(nb)]
     for i in range(warmup):
-        gv.search(model, index, batches[i % nb], k, kappa)
+        fn(model, index, batches[i % nb], k, kappa)
     torch.cuda.synchronize()
     gv.profile_read()
     gv.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        gv.search(model, index, batches[i % nb], k, kappa)
+        fn(model, index, batches[i % nb], k, kappa)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     gv.profile_enable(False)
@@ -273,13 +275,17 @@ def precision_report(gv, model, index, fmt, X, QT, gt, k, kappa0, nq_err=64):
     cid, csc = gv.score_topk(index, qhat, t, kappa0)
     ids, sc = gv.search(model, index, Qe, k, kappa0)
     torch.cuda.synchronize()
-    Xc = X[cid.long()].double()                                  # nq x kappa x D
+    # ids outside [0, n) (fewer valid candidates than asked for) are left out of the statistics
+    n = X.shape[0]
+    okc = (cid >= 0) & (cid < n)
+    Xc = X[torch.where(okc, cid, 0).long()].double()             # nq x kappa x D
     ip = (Xc * Qe.double()[:, None, :]).sum(-1)
     scale = Xc.norm(dim=2) * Qe.double().norm(dim=1, keepdim=True)
-    rel = ((csc.double() - ip).abs() / scale).flatten()
-    Xf = X[ids.long()].double()
+    rel = ((csc.double() - ip).abs() / scale)[okc]
+    okf = (ids >= 0) & (ids < n)
+    Xf = X[torch.where(okf, ids, 0).long()].double()
     ipf = (Xf * Qe.double()[:, None, :]).sum(-1)
-    relf = ((sc.double() - ipf).abs() / (Xf.norm(dim=2) * Qe.double().norm(dim=1, keepdim=True))).flatten()
+    relf = ((sc.double() - ipf).abs() / (Xf.norm(dim=2) * Qe.double().norm(dim=1, keepdim=True)))[okf]
     q = torch.tensor([0.5, 0.99], dtype=torch.float64, device=rel.device)
     rq = torch.quantile(rel, q).tolist()
     return {"fmt": fmt, "kappa": kappa0, "recall_at_10": rec, "kappa_for_recall_0.9": kappa_used,
@@ -349,8 +355,8 @@ def main():
         del src, dst
         log("[bench] calibration copy: 3 x 1 GiB")
 
-    if a.splits or a.qpw:
-        gv.search_tuning(splits=a.splits, qpw=a.qpw)
+    if a.splits or a.qpw or a.cap:
+        gv.search_tuning(splits=a.splits, qpw=a.qpw, cap=a.cap)
     nrq = min(a.recall_queries, QT.shape[0])
     gt = exact_topk_device(X, QT[:nrq], wl.k)
 
@@ -396,6 +402,16 @@ def main():
                 f"roofline), select {ms_sel:.3f} ms")
             if fmt == a.fmt and m == a.m:
                 main_rec = (ent, dt, steps)
+        if fmt == "fp16" and not a.no_sweep and wl.d == 160:
+            # the lazy inner product (Algorithm 3) against the eager one at m = 1
+            dt, ms_scan, ms_sel = time_search(gv, model, index, QT, 1, wl.k, kap, a.single_queries, 5,
+                                              fn=gv.search_lazy)
+            lazy = {"fmt": fmt, "m": 1, "kappa": kap, "variant": "lazy inner product (Algorithm 3)",
+                    "qps": a.single_queries / dt, "ms_per_batch": dt / a.single_queries * 1e3, "scan_ms": ms_scan,
+                    "select_ms": ms_sel}
+            sweep.append(lazy)
+            log(f"[bench]   {fmt} m=1 lazy: {lazy['qps']:,.0f} q/s, batch {lazy['ms_per_batch']:.3f} ms, "
+                f"full scan {ms_scan:.3f} ms")
         del index
         torch.cuda.empty_cache()
 

@@ -287,6 +287,22 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
                     int32_t k, int32_t kappa, int32_t* out_ids, float* out_scores, void* stream);
 
 /*
+ * gv_search_lazy -- gv_search with the lazy inner product of Algorithm 3
+ * instead of the eager one (Algorithm 4): no projection pass; each work item
+ * of the scan computes the views q_c = fl32(A_c q) of the cluster it visits
+ * (FP64 accumulation, the same arithmetic as gv_search's projection of small
+ * batches) and their FP16 view, then scores as gv_search does.  Results equal
+ * gv_search's bit for bit.  Exists to measure the paper's lazy alternative:
+ * the exhaustive scan visits every cluster from many work items, so the
+ * projections are repeated per work item.  Supported: FP16 storage, a padded
+ * reduced length of 160 (gv_padded_dim(d) == 160), 1 <= m <= 16, an index that
+ * keeps X, and no qpw override.  Errors: as gv_search; GV_EUNSUPPORTED
+ * otherwise.
+ */
+gv_status gv_search_lazy(const gv_model* model, const gv_index* index, const float* Q, int64_t m,
+                         int32_t k, int32_t kappa, int32_t* out_ids, float* out_scores, void* stream);
+
+/*
  * gv_search_noalloc -- gv_search for callers that cannot allocate device memory:
  * code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation.  Same arguments, stages and results as gv_search (bit for bit),
@@ -463,8 +479,9 @@ gv_status gv_rerank_stored(const gv_index* index, const float* qc, int64_t m, co
  * splits = row ranges per query block (1..4096), qpw = queries per wavefront
  * (32, 64 or 128), cap = key slots per (query, row range) list; a list is
  * compacted to its kappa best (ties at the kappa-th score kept) when it may
- * overflow before the next check (512..2048; a search with cap < kappa + 417
- * fails with GV_EINVAL).  Results
+ * overflow before the next check (64..2048; a search whose launch shapes leave
+ * a list no room above kappa -- see gv_scan_plan's list_limit -- fails with
+ * GV_EINVAL or GV_EUNSUPPORTED).  Results
  * do not depend on these; only speed does.  Errors: GV_EINVAL.
  */
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap);

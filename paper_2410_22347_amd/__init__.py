@@ -32,7 +32,7 @@ EXPORTED = [
     "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored", "gv_augment",
     "gv_moments_update", "gv_fit_from_stats", "gv_batch_counts", "gv_eig_step_limit",
     "gv_model_save", "gv_model_load", "gv_model_file_info", "gv_model_sphering", "gv_scan_plan",
-    "gv_search_noalloc", "gv_search_noalloc_capacity", "gv_index_reproject", "gv_index_rows",
+    "gv_search_noalloc", "gv_search_noalloc_capacity", "gv_index_reproject", "gv_index_rows", "gv_search_lazy",
 ]
 
 
@@ -81,6 +81,7 @@ _sig("gv_index_reproject", [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.c_int, _vp, ct
 _sig("gv_index_rows", [_vp, ctypes.POINTER(_i64)])
 _sig("gv_search", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_search_noalloc", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
+_sig("gv_search_lazy", [_vp, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_search_noalloc_capacity", [], _i64)
 _sig("gv_project", [_vp, ctypes.c_int, _vp, _i64, _vp, _vp, _vp, _vp])
 _sig("gv_score_topk", [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp])
@@ -310,6 +311,18 @@ def search_noalloc_into(model: Model, index: Index, Q, k: int, kappa: int, out_i
 
 def search_noalloc_capacity() -> int:
     return int(_lib.gv_search_noalloc_capacity())
+
+
+def search_lazy(model: Model, index: Index, Q, k: int, kappa: int):
+    """The search with the lazy inner product of Algorithm 3 (gv_search_lazy)."""
+    import torch
+    _dev_f32(Q)
+    m = Q.shape[0]
+    ids = torch.empty((m, k), dtype=torch.int32, device=Q.device)
+    sc = torch.empty((m, k), dtype=torch.float32, device=Q.device)
+    _check(_lib.gv_search_lazy(model._h, index._h, _ptr(Q), m, k, kappa, _ptr(ids), _ptr(sc), _stream()),
+           "gv_search_lazy")
+    return ids, sc
 
 
 def augment(V, kind: str):

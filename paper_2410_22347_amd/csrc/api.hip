@@ -606,6 +606,19 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
   });
 }
 
+gv_status gv_search_lazy(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int32_t k,
+                         int32_t kappa, int32_t* out_ids, float* out_scores, void* stream) {
+  return guarded([&]() -> gv_status {
+    if (!valid(model) || !valid(index)) return GV_ENOTFIT;
+    GV_REQUIRE(model->C == index->C && model->d == index->d && model->D == index->D,
+               "gv_search_lazy: model and index shapes differ");
+    GV_TRY(check_search_args(index, m, k, kappa));
+    if (m == 0) return GV_OK;
+    GV_REQUIRE(Q && out_ids, "gv_search_lazy: NULL argument");
+    return search_lazy_impl(model, index, Q, m, k, kappa, out_ids, out_scores, (hipStream_t)stream);
+  });
+}
+
 // ---------------------------------------------------------------------------- Euclidean adaptation
 gv_status gv_augment(const float* V, int64_t n, int32_t D, int32_t kind, float* out, void* stream) {
   return guarded([&]() -> gv_status {
@@ -856,7 +869,7 @@ gv_status gv_scan_plan(int64_t n, int64_t n_pad, int32_t C, gv_format fmt, int32
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap) {
   if (splits < 0 || splits > 4096) return GV_EINVAL;
   if (qpw != 0 && qpw != 32 && qpw != 64 && qpw != 128) return GV_EINVAL;
-  if (cap != 0 && (cap < 512 || cap > 2048)) return GV_EINVAL;
+  if (cap != 0 && (cap < 64 || cap > 2048)) return GV_EINVAL;
   g_splits = splits;
   g_qpw = qpw;
   g_cap = cap;

@@ -268,6 +268,8 @@ gv_status search_plan(const gv_model* model, const gv_index* index, int64_t m, i
                       int d_search = 0, bool stored = false);
 gv_status search_run(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int k, int kappa,
                      int32_t* out_ids, float* out_scores, const SearchPlan& plan, void* workspace, hipStream_t st);
+gv_status search_lazy_impl(const gv_model* model, const gv_index* idx, const float* Q, int64_t m, int k, int kappa,
+                           int32_t* out_ids, float* out_scores, hipStream_t st);
 gv_status rerank_impl(const gv_index* index, const float* Q, int64_t m, const int32_t* cand,
                       int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
 gv_status rerank_stored_impl(const gv_index* index, const float* qc, int64_t m, const int32_t* cand,

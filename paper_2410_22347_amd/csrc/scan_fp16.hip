@@ -11,4 +11,13 @@ gv_status dispatch_scan(int dp, const scan::Shape& sh, const scan::ScoreArgs& ar
 template gv_status dispatch_scan<GV_FP16, scan::kFilter>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
 template gv_status dispatch_scan<GV_FP16, scan::kDense>(int, const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
 
+template <int MODE>
+gv_status dispatch_scan_lazy(const scan::Shape& sh, const scan::ScoreArgs& args, hipStream_t st) {
+  scan::launch_lazy<MODE>(sh, args, st);
+  GV_HIP(hipGetLastError());
+  return GV_OK;
+}
+template gv_status dispatch_scan_lazy<scan::kFilter>(const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
+template gv_status dispatch_scan_lazy<scan::kDense>(const scan::Shape&, const scan::ScoreArgs&, hipStream_t);
+
 }  // namespace gv

@@ -343,8 +343,9 @@ void keep_pool(int dev) {
   done[dev] = true;
 }
 
-// smallest list capacity the scan accepts for a given kappa: a list is checked
-// for overflow every 2P + 1 tiles (P <= 6) and takes at most 32 keys per tile
+// a list capacity every launch shape accepts for kappa: a list is checked for
+// overflow at least every 13 tiles and takes at most 32 keys per tile (each
+// plan checks its own shapes: list_limit > kappa)
 int min_list_cap(int kappa) { return kappa + kRows * 13 + 1; }
 
 namespace {
@@ -399,8 +400,8 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
     return GV_EUNSUPPORTED;
   }
   p->cap = tuned_cap() > 0 ? tuned_cap() : kCap;
-  if (p->cap < min_list_cap(kappa) || p->cap > kCap) {
-    set_error("candidate list capacity must lie in [kappa + 417, 2048]");
+  if (p->cap <= kappa || p->cap > kCap) {
+    set_error("candidate list capacity must lie in (kappa, 2048]");
     return GV_EINVAL;
   }
   p->levels = cascade(n, kappa);
@@ -450,8 +451,15 @@ gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int 
                         kappa, p);
 }
 
+// views made inside the scan (Algorithm 3) instead of qhat/t
+struct LazyViews {
+  const double* A;
+  const float* Q;
+  int d, D, ds;
+};
+
 gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const void* qhat, const float* t, int64_t m,
-                   int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st) {
+                   int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st, const LazyViews* lazy = nullptr) {
   uint64_t* buf = (uint64_t*)(ws + p.off_buf);
   int32_t* cnt = (int32_t*)(ws + p.off_cnt);
   float* seed = p.has_dense ? (float*)(ws + p.off_seed) : nullptr;
@@ -459,6 +467,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
   const int fmt = idx->fmt;
 
   ScoreArgs args{};
+  Shape sh_cur{};
   args.xlow = (const uint8_t*)idx->xlow;
   args.ids = idx->ids;
   args.scale = idx->scale;
@@ -476,11 +485,23 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
   args.dps = idx->dp;
   args.kappa = kappa;
   args.cap = p.cap;
+  if (lazy) {
+    args.lazy_A = lazy->A;
+    args.lazy_Q = lazy->Q;
+    args.lazy_d = lazy->d;
+    args.lazy_D = lazy->D;
+    args.lazy_ds = lazy->ds;
+  }
+  auto dispatch = [&](bool dense) -> gv_status {
+    if (lazy) return dense ? dispatch_scan_lazy<kDense>(sh_cur, args, st) : dispatch_scan_lazy<kFilter>(sh_cur, args, st);
+    return dense ? dispatch_fmt<kDense>(fmt, p.dp, sh_cur, args, st) : dispatch_fmt<kFilter>(fmt, p.dp, sh_cur, args, st);
+  };
 
   gv_status s = GV_OK;
   if (p.has_dense) hipLaunchKernelGGL(k_seed_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, seed);
   for (size_t li = 0; li < p.levels.size() && s == GV_OK; ++li) {
     const Shape& sh = p.shapes[li];
+    sh_cur = sh;
     const bool last = li + 1 == p.levels.size();
     args.seed = li == 0 ? nullptr : seed;
     args.R = sh.R;
@@ -488,7 +509,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     args.stride = (int)p.levels[li];
     args.xcd_map = sh.xcd_map;
     if (p.has_dense && li == 0) {
-      s = dispatch_fmt<kDense>(fmt, p.dp, sh, args, st);
+      s = dispatch(true);
       if (s == GV_OK)
         hipLaunchKernelGGL(k_dense_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, dense, m, p.ns, kappa,
                            seed);
@@ -499,7 +520,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
       return GV_EDEVICE;
     }
     if (last) profile_mark(st, 0, true);
-    s = dispatch_fmt<kFilter>(fmt, p.dp, sh, args, st);
+    s = dispatch(false);
     if (last) profile_mark(st, 0, false);
     if (s != GV_OK) break;
     if (last) {
@@ -616,6 +637,41 @@ gv_status search_run(const gv_model* model, const gv_index* idx, const float* Q,
   else
     GV_TRY(rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st));
   return GV_OK;
+}
+
+// The search with the lazy inner product (Algorithm 3): no S1 pass; the scan
+// projects q_c = A_c q for the cluster it visits, in each work item.  FP16
+// storage, padded length 160, batches small enough for one shared query block
+// whose eager projection runs the same arithmetic (m <= 16).
+gv_status search_lazy_impl(const gv_model* model, const gv_index* idx, const float* Q, int64_t m, int k, int kappa,
+                           int32_t* out_ids, float* out_scores, hipStream_t st) {
+  if (m == 0) return GV_OK;
+  if (idx->fmt != GV_FP16 || idx->dp != 160 || m > kSmallM || !idx->X) {
+    set_error("lazy search: needs FP16 storage, a padded reduced length of 160, m <= 16 and an index that keeps X");
+    return GV_EUNSUPPORTED;
+  }
+  ScanPlan p;
+  GV_TRY(plan_scan(idx, m, kappa, &p));
+  for (const Shape& sh : p.shapes)
+    if (!sh.shared || sh.nb != 1) {
+      set_error("lazy search: the launch shape must be one shared block of 32 queries (no qpw override)");
+      return GV_EUNSUPPORTED;
+    }
+  keep_pool(idx->device);
+  const size_t off_cand = align256(p.bytes), off_csc = align256(off_cand + sizeof(int32_t) * m * kappa);
+  const size_t bytes = align256(off_csc + sizeof(float) * m * kappa);
+  uint8_t* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, bytes, st) != hipSuccess) {
+    set_error("search scratch allocation failed");
+    return GV_ENOMEM;
+  }
+  LazyViews lv{model->A, Q, model->d, model->D, model->d};
+  int32_t* cand = (int32_t*)(ws + off_cand);
+  float* csc = (float*)(ws + off_csc);
+  gv_status s = run_scan(idx, p, ws, nullptr, nullptr, m, kappa, cand, csc, st, &lv);
+  if (s == GV_OK) s = rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st);
+  (void)hipFreeAsync(ws, st);
+  return s;
 }
 
 // ============================================================================ S4

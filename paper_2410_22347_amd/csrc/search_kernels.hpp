@@ -60,6 +60,12 @@ struct ScoreArgs {
   int dps;      // stored (padded) row length: tiles are 32 * dps elements apart
   int stride;   // scan every stride-th tile
   int xcd_map;  // 1: workgroups sharing rows are pinned to one XCD
+  // lazy inner product (Algorithm 3): the scan projects each visited cluster's
+  // view itself instead of reading qhat/qscale
+  const double* lazy_A;  // C x lazy_d x lazy_D, FP64 (the model's stacked A_c)
+  const float* lazy_Q;   // m x lazy_D FP32 queries
+  int lazy_d, lazy_D;    // the model's reduced and full dimension
+  int lazy_ds;           // leading coordinates in the view (d_search)
 };
 
 __device__ inline void wave_sync() {
@@ -255,7 +261,43 @@ __device__ inline float max16(const f32x16& v) {
 // output layout: rows (i % 4) + 8 * (i / 4) + 4 * h, column = lane % 32)
 __device__ constexpr int acc_row(int i, int h) { return (i & 3) + 8 * (i >> 2) + 4 * h; }
 
-template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC, bool FULL, bool WGT, int PL>
+// The view of one query for cluster c as the lazy inner product computes it
+// (Algorithm 3, the projection A_c q made where the cluster is visited):
+// v_j = fl32(A_c(j, :) q) with FP64 accumulation (lane-strided sums, butterfly
+// reduction, lane 0's value -- the same arithmetic as the eager projection of
+// small batches), t = the power of two putting max |v_j| (j < ds) into
+// (T/2, T], and the FP16 view rnd(v_j / t) for j < ds, zero up to dp.
+// One wavefront; writes dp halves to view[] and returns t.
+__device__ inline float lazy_view(const double* __restrict__ A, const float* __restrict__ q, int c, int d, int D,
+                                  int ds, int dp, uint16_t* view) {
+  const int lane = threadIdx.x & 63;
+  const double* Ac = A + (int64_t)c * d * D;
+  float amax = 0.0f;
+  float vals[4];  // dp <= 256: lane l keeps v_j for j = 64 u + l
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    vals[u] = 0.0f;
+    for (int jj = 0; jj < 64 && 64 * u + jj < ds; ++jj) {
+      const double* a = Ac + (int64_t)(64 * u + jj) * D;
+      double sacc = 0.0;
+      for (int k = lane; k < D; k += 64) sacc += a[k] * (double)q[k];
+      for (int o = 32; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o);
+      const float v = (float)__shfl(sacc, 0);  // lane 0's sum, as the eager projection keeps
+      if (jj == lane) vals[u] = v;
+      amax = fmaxf(amax, fabsf(v));
+    }
+  }
+  const float t = pow2_scale(amax, 65504.0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = u * 64 + lane;
+    if (j < dp) view[j] = j < ds ? to_fp16((double)vals[u] / (double)t) : (uint16_t)0;
+  }
+  return t;
+}
+
+template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC, bool FULL, bool WGT, int PL,
+          bool LAZY = false>
 __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   using Op = MfmaOp<FMT>;
   using S = typename Op::S;
@@ -273,6 +315,10 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   static_assert(CAPL - kRows * (U + 1) >= 256 + kRows, "the staging must hold kappa <= 256 plus a tile");
   __shared__ WaveSmem<QW, CAPL> s_wave[4];
   __shared__ __attribute__((aligned(16))) uint8_t s_ring[WGT ? PL * TB : 16];
+  // lazy views: per wavefront, its queries' FP16 views of the visited cluster
+  static_assert(!LAZY || (FMT == GV_FP16 && SHARED && NB == 1), "lazy views: FP16 storage, one shared query block");
+  __shared__ __attribute__((aligned(16))) uint16_t s_lazy[LAZY ? 4 * QW * KS * 16 : 8];
+  __shared__ float s_lazy_t[LAZY ? 4 * QW : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, col = lane & 31;
   WaveSmem<QW, CAPL>& w = s_wave[wave];
@@ -453,7 +499,32 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
     const int64_t tiles_end = uniform64(a.offsets[c + 1]) / kRows;  // first tile after the segment
     const int64_t v1 = std::min<int64_t>(v_end, (tiles_end + stride - 1) / stride);
     const int64_t real_end = uniform64(a.seg_end[c]);
-    {
+    if constexpr (LAZY) {
+      // Algorithm 3: the views of this cluster are made here, for the block's
+      // queries, into this wavefront's LDS, then taken as the eager views are
+      constexpr int DP = KS * 16;
+      uint16_t* vw = s_lazy + wave * QW * DP;
+      const int64_t nq = std::min<int64_t>(QW, a.m - q0);
+      for (int i = 0; i < nq; ++i) {
+        const float t = lazy_view(a.lazy_A, a.lazy_Q + (q0 + i) * a.lazy_D, c, a.lazy_d, a.lazy_D, a.lazy_ds, DP,
+                                  vw + i * DP);
+        if (lane == 0) s_lazy_t[wave * QW + i] = t;
+      }
+      wave_sync();
+      const float sc = uniformf(a.scale[c]) * (1.0f / Op::kScale);
+      const int64_t q = q0 + col;
+      const bool qv = q < a.m;
+      const uint16_t* qp = vw + (qv ? col : 0) * DP + half * Op::EPL;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const typename Op::QS raw = *(const typename Op::QS*)(qp + s * Op::KM);
+        bq[0][s] = qv ? raw : zero_op<T>();
+      }
+      st[0] = sc * (qv ? s_lazy_t[wave * QW + col] : 1.0f);
+      inv_st[0] = 1.0f / st[0];
+      tau_s[0] = w.tau[col] * inv_st[0];
+      wave_sync();  // the views are in registers before the next segment rewrites them
+    } else {
       const float sc = uniformf(a.scale[c]) * (1.0f / Op::kScale);
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
         constexpr int nb = decltype(nbc)::value;
@@ -726,6 +797,19 @@ void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
                        dim3(256), 0, st, args);
 }
 
+// The lazy variant (Algorithm 3): FP16 storage, one shared block of up to 32
+// queries, padded length 160.
+template <int MODE>
+void launch_lazy(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
+  using K = KernelCfg<GV_FP16, 10, 1, true>;
+  if (MODE == kFilter && args.stride == 1)
+    hipLaunchKernelGGL((k_scan<GV_FP16, 10, 1, true, MODE, K::P, K::DEF, K::OC, true, K::W, K::PL, true>),
+                       dim3(sh.grid), dim3(256), 0, st, args);
+  else
+    hipLaunchKernelGGL((k_scan<GV_FP16, 10, 1, true, MODE, K::P, K::DEF, K::OC, false, K::W, K::PL, true>),
+                       dim3(sh.grid), dim3(256), 0, st, args);
+}
+
 // The instantiation launch_score picks for a shape, described on the host.
 struct ScanLimits {
   int nb = 0, U = 0, CAPL = 0, P = 0, PL = 0, occupancy = 0;
@@ -796,5 +880,8 @@ gv_status dispatch_ks(int dp, const Shape& sh, const ScoreArgs& args, hipStream_
 // per-format entry points (scan_fp32.hip, scan_fp16.hip, ...)
 template <int FMT, int MODE>
 gv_status dispatch_scan(int dp, const scan::Shape& sh, const scan::ScoreArgs& args, hipStream_t st);
+// the lazy variant (scan_fp16.hip)
+template <int MODE>
+gv_status dispatch_scan_lazy(const scan::Shape& sh, const scan::ScoreArgs& args, hipStream_t st);
 
 }  // namespace gv

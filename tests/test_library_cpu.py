@@ -108,7 +108,7 @@ def test_host_argument_errors():
     assert lib.gv_model_stats(None, None, None, None, None, None, None, None) == -4
     assert lib.gv_host_eigh(0, None, None, None) == -1
     assert lib.gv_search_tuning(0, 48, 0) == -1
-    assert lib.gv_search_tuning(0, 0, 100) == -1
+    assert lib.gv_search_tuning(0, 0, 50) == -1
     assert lib.gv_search_tuning(5000, 0, 0) == -1
     assert lib.gv_search_tuning(0, 0, 0) == 0
     lib.gv_model_destroy(None)
@@ -170,7 +170,7 @@ def test_scan_plan_invariants():
     import paper_2410_22347_amd as gv
     lib = gv._lib
     checked = refused = 0
-    tunings = [(0, 0, 0), (24, 0, 0), (1, 0, 0), (4, 0, 640), (0, 64, 0), (0, 128, 0), (0, 32, 1024)]
+    tunings = [(0, 0, 0), (24, 0, 0), (1, 0, 0), (4, 0, 640), (0, 64, 0), (0, 128, 0), (0, 32, 1024), (0, 0, 320)]
     for splits, qpw, cap in tunings:
         assert lib.gv_search_tuning(splits, qpw, cap) == 0
         try:
