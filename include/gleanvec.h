@@ -522,6 +522,42 @@ gv_status gv_scan_plan(int64_t n, int64_t n_pad, int32_t C, gv_format fmt, int32
                        int32_t kappa, gv_scan_level* levels, int32_t max_levels, int32_t* n_levels,
                        int64_t* list_keys, int64_t* scratch_bytes);
 
+/* Result of gv_autotune. */
+typedef struct {
+  int32_t splits, qpw, cap;  /* the fastest launch shape (0: automatic) */
+  double ms;                 /* its time per search */
+  double ms_automatic;       /* the automatic shape's time per search */
+  int32_t candidates;        /* shapes timed */
+} gv_tune_result;
+
+/*
+ * gv_autotune -- time candidate launch shapes of stages S2/S3 (row ranges per
+ * query block, queries per wavefront, list capacity; the automatic choice
+ * among them) on this index with these m queries, `reps` searches each on
+ * `stream`, and keep the fastest for the search's shape class -- storage
+ * format, padded reduced length, batch class (1, <= 32, <= 64, <= 256, <= 1024,
+ * <= 4096, more) and size class (floor(log2 stored rows)) -- in a process-wide
+ * table.  Later searches of that class (gv_search, gv_search_batched, ...) use
+ * the table's shape unless the thread set overrides with gv_search_tuning.
+ * Results never depend on the launch shape, only speed does.  Q: device
+ * m x D FP32; the index must keep X.  out (host, may be NULL) receives the
+ * choice.  Synchronises `stream`.  Errors: as gv_search; GV_EUNSUPPORTED if no
+ * candidate can run the search.
+ */
+gv_status gv_autotune(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int32_t k,
+                      int32_t kappa, int32_t reps, gv_tune_result* out, void* stream);
+
+/* The autotuner's table as a text file (one line per shape class:
+ * fmt d_pad batch_class size_class splits qpw cap ms), written or merged into
+ * the process's table.  Errors: GV_EINVAL (path, malformed line), GV_EDEVICE. */
+gv_status gv_tuning_table_save(const char* path);
+gv_status gv_tuning_table_load(const char* path);
+/* The table's launch shape for a class, GV_EUNSUPPORTED if it has none. */
+gv_status gv_tuning_lookup(int32_t fmt, int32_t d_pad, int64_t m, int64_t n_rows, int32_t* splits, int32_t* qpw,
+                           int32_t* cap);
+/* Empty the table. */
+void gv_tuning_table_clear(void);
+
 /*
  * gv_padded_dim -- the padded row length d_pad used for a reduced dimension d:
  * the smallest of 32, 64, 128, 160, 192, 256 that is >= d (gv_project and

@@ -33,6 +33,7 @@ EXPORTED = [
     "gv_moments_update", "gv_fit_from_stats", "gv_batch_counts", "gv_eig_step_limit",
     "gv_model_save", "gv_model_load", "gv_model_file_info", "gv_model_sphering", "gv_scan_plan",
     "gv_search_noalloc", "gv_search_noalloc_capacity", "gv_index_reproject", "gv_index_rows", "gv_search_lazy",
+    "gv_autotune", "gv_tuning_table_save", "gv_tuning_table_load", "gv_tuning_lookup", "gv_tuning_table_clear",
 ]
 
 
@@ -113,6 +114,18 @@ _sig("gv_moments", [_vp, _i64, _i32, _vp, _i32, _vp, _vp])
 _sig("gv_loss_grad", [_i32, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp, _vp])
 _sig("gv_profile_read", [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(_i64)])
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("splits", ctypes.c_int32), ("qpw", ctypes.c_int32), ("cap", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("ms_automatic", ctypes.c_double), ("candidates", ctypes.c_int32)]
+
+
+_sig("gv_autotune", [_vp, _vp, _vp, _i64, _i32, _i32, _i32, ctypes.POINTER(_TuneResult), _vp])
+_sig("gv_tuning_table_save", [ctypes.c_char_p])
+_sig("gv_tuning_table_load", [ctypes.c_char_p])
+_sig("gv_tuning_lookup", [_i32, _i32, _i64, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+_sig("gv_tuning_table_clear", [], None)
 
 
 def _check(status: int, where: str):
@@ -435,6 +448,37 @@ def rerank(index: Index, Q, cand_ids, k: int):
 
 def search_tuning(splits: int = 0, qpw: int = 0, cap: int = 0):
     _check(_lib.gv_search_tuning(splits, qpw, cap), "gv_search_tuning")
+
+
+def autotune(model: Model, index: Index, Q, k: int, kappa: int, reps: int = 3):
+    """gv_autotune: time candidate launch shapes for this search's shape class and
+    keep the fastest in the process's table; returns the choice as a dict."""
+    _dev_f32(Q)
+    r = _TuneResult()
+    _check(_lib.gv_autotune(model._h, index._h, _ptr(Q), Q.shape[0], k, kappa, reps, ctypes.byref(r), _stream()),
+           "gv_autotune")
+    return dict(splits=r.splits, qpw=r.qpw, cap=r.cap, ms=r.ms, ms_automatic=r.ms_automatic,
+                candidates=r.candidates)
+
+
+def tuning_table_save(path: str):
+    _check(_lib.gv_tuning_table_save(os.fsencode(path)), "gv_tuning_table_save")
+
+
+def tuning_table_load(path: str):
+    _check(_lib.gv_tuning_table_load(os.fsencode(path)), "gv_tuning_table_load")
+
+
+def tuning_lookup(fmt, d_pad: int, m: int, n_rows: int):
+    """The table's (splits, qpw, cap) for a shape class, or None."""
+    f = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+    sp, qpw, cap = _i32(), _i32(), _i32()
+    st = _lib.gv_tuning_lookup(f, d_pad, m, n_rows, ctypes.byref(sp), ctypes.byref(qpw), ctypes.byref(cap))
+    return None if st != 0 else (sp.value, qpw.value, cap.value)
+
+
+def tuning_table_clear():
+    _lib.gv_tuning_table_clear()
 
 
 def padded_dim(d: int) -> int:

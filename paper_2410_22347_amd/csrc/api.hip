@@ -751,12 +751,13 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
     GV_REQUIRE(models && indexes && Q && m && out_ids, "gv_search_batched: NULL argument");
     int dev = 0;
     GV_HIP(hipGetDevice(&dev));
-    std::vector<SearchPlan> plans(n_coll);
-    // collection i runs on side stream i % kBatchStreams; collections on one
-    // stream run one after the other and share that stream's workspace slot
-    std::vector<size_t> slot(kBatchStreams, 0);
+    std::vector<BatchEntry> ent;
+    // every search keeps a workspace of its own: its lists live from its
+    // cascade levels, through the shared full-scan launches, to its final select
     std::vector<uintptr_t> key{(uintptr_t)n_coll, (uintptr_t)k, (uintptr_t)kappa, (uintptr_t)stream, (uintptr_t)dev,
-                               (uintptr_t)tuned_splits(), (uintptr_t)tuned_qpw(), (uintptr_t)tuned_cap()};
+                               (uintptr_t)tuned_splits(), (uintptr_t)tuned_qpw(), (uintptr_t)tuned_cap(),
+                               (uintptr_t)tuning_table_version()};
+    size_t ws_bytes = 0;
     for (int i = 0; i < n_coll; ++i) {
       const gv_model* md = models[i];
       const gv_index* ix = indexes[i];
@@ -765,14 +766,20 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
       GV_REQUIRE(ix->device == dev, "gv_search_batched: index on another device");
       GV_TRY(check_search_args(ix, m[i], k, kappa));
       GV_REQUIRE(m[i] == 0 || (Q[i] && out_ids[i]), "gv_search_batched: NULL query or output");
-      if (m[i] > 0) GV_TRY(search_plan(md, ix, m[i], kappa, &plans[i]));
-      if (m[i] > 0) slot[i % kBatchStreams] = std::max(slot[i % kBatchStreams], (plans[i].bytes + 255) / 256 * 256);
+      if (m[i] > 0) {
+        BatchEntry b{md, ix, Q[i], m[i], out_ids[i], out_scores ? out_scores[i] : nullptr, SearchPlan{}, nullptr};
+        GV_TRY(search_plan(md, ix, m[i], kappa, &b.plan));
+        b.ws = (uint8_t*)(uintptr_t)ws_bytes;  // offset until the workspace exists
+        ws_bytes += (b.plan.bytes + 255) / 256 * 256;
+        ent.push_back(b);
+      }
       // handles enter the key by generation: a handle freed and another created at
       // the same address must not replay a graph that holds the old one's buffers
       for (uintptr_t v : {(uintptr_t)md->gen, (uintptr_t)ix->gen, (uintptr_t)Q[i], (uintptr_t)m[i],
                           (uintptr_t)out_ids[i], (uintptr_t)(out_scores ? out_scores[i] : nullptr)})
         key.push_back(v);
     }
+    if (ent.empty()) return GV_OK;
     hipStream_t st = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g_batch_mu);
     if (g_batch.exec && g_batch.key == key) {  // same batch as last time: replay
@@ -782,11 +789,15 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
     }
     release_batch(g_batch);
     GV_TRY(side_streams(dev));
-    std::vector<size_t> off(kBatchStreams + 1, 0);
-    for (int j = 0; j < kBatchStreams; ++j) off[j + 1] = off[j] + slot[j];
+    int n_cu = 0;
+    GV_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const size_t qbytes = batched_queue_bytes((int)ent.size());
     void* ws = nullptr;
-    GV_HIP(hipMalloc(&ws, std::max<size_t>(off[kBatchStreams], 256)));
-    // capture every collection's search as a branch of one graph
+    GV_HIP(hipMalloc(&ws, ws_bytes + qbytes));
+    for (BatchEntry& b : ent) b.ws = (uint8_t*)ws + (uintptr_t)b.ws;
+    uint8_t* qmem = (uint8_t*)ws + ws_bytes;
+    // capture: projections and cascades as branches, the full scans of all
+    // searches as persistent queue launches, the selects and reranks as branches
     gv_status s = GV_OK;
     hipGraph_t graph = nullptr;
     hipStream_t org = g_origin[dev];
@@ -796,20 +807,9 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
       return GV_EDEVICE;
     }
     g_capturing = true;
-    hipError_t e = hipEventRecord(g_fork[dev], org);
-    for (int j = 0; j < kBatchStreams && e == hipSuccess; ++j) e = hipStreamWaitEvent(g_side[dev][j], g_fork[dev], 0);
-    if (e != hipSuccess) s = GV_EDEVICE;
-    for (int i = 0; i < n_coll && s == GV_OK; ++i) {
-      if (m[i] == 0) continue;
-      const int j = i % kBatchStreams;
-      s = search_run(models[i], indexes[i], Q[i], m[i], k, kappa, out_ids[i], out_scores ? out_scores[i] : nullptr,
-                     plans[i], (uint8_t*)ws + off[j], g_side[dev][j]);
-    }
-    for (int j = 0; j < kBatchStreams; ++j) {
-      if (hipEventRecord(g_join[dev][j], g_side[dev][j]) != hipSuccess ||
-          hipStreamWaitEvent(org, g_join[dev][j], 0) != hipSuccess)
-        s = s == GV_OK ? GV_EDEVICE : s;
-    }
+    std::vector<uint8_t> upload;
+    s = batched_run(ent, k, kappa, org, g_side[dev], kBatchStreams, g_fork[dev], g_join[dev], qmem, qbytes, n_cu,
+                    &upload);
     g_capturing = false;
     const hipError_t ec = hipStreamEndCapture(org, &graph);
     if (s == GV_OK && ec != hipSuccess) {
@@ -819,6 +819,11 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
     hipGraphExec_t exec = nullptr;
     if (s == GV_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
       set_error("gv_search_batched: graph instantiation failed");
+      s = GV_EDEVICE;
+    }
+    // the queue launches' arguments and piece offsets: written once, read by every replay
+    if (s == GV_OK && !upload.empty() && hipMemcpy(qmem, upload.data(), upload.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("gv_search_batched: upload of the queue arguments failed");
       s = GV_EDEVICE;
     }
     if (graph) (void)hipGraphDestroy(graph);

@@ -268,6 +268,21 @@ gv_status search_plan(const gv_model* model, const gv_index* index, int64_t m, i
                       int d_search = 0, bool stored = false);
 gv_status search_run(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int k, int kappa,
                      int32_t* out_ids, float* out_scores, const SearchPlan& plan, void* workspace, hipStream_t st);
+// one search of a batched launch sequence, with its own workspace
+struct BatchEntry {
+  const gv_model* model;
+  const gv_index* idx;
+  const float* Q;
+  int64_t m;
+  int32_t* out_ids;
+  float* out_scores;
+  SearchPlan plan;
+  uint8_t* ws;
+};
+gv_status batched_run(std::vector<BatchEntry>& entries, int k, int kappa, hipStream_t org, hipStream_t* side,
+                      int nside, hipEvent_t fork, hipEvent_t* join, uint8_t* qmem, size_t qbytes, int n_cu,
+                      std::vector<uint8_t>* upload);
+size_t batched_queue_bytes(int n_entries);
 gv_status search_lazy_impl(const gv_model* model, const gv_index* idx, const float* Q, int64_t m, int k, int kappa,
                            int32_t* out_ids, float* out_scores, hipStream_t st);
 gv_status rerank_impl(const gv_index* index, const float* Q, int64_t m, const int32_t* cand,
@@ -319,6 +334,16 @@ void set_eig_step_limit(long max_steps);
 int tuned_splits();
 int tuned_qpw();
 int tuned_cap();
+// Launch overrides of S2/S3 (0: automatic).  The calling thread's overrides
+// (gv_search_tuning) come first; else the autotuner's table entry for the
+// search's shape class (format, padded length, batch class, size class).
+struct Tuning {
+  int splits = 0, qpw = 0, cap = 0;
+};
+Tuning effective_tuning(int fmt, int dp, int64_t m, int64_t n_rows);
+bool tuning_table_lookup(int fmt, int dp, int64_t m, int64_t n_rows, Tuning* t);
+void tuning_table_store(int fmt, int dp, int64_t m, int64_t n_rows, const Tuning& t, double ms);
+uint64_t tuning_table_version();
 // the calling thread's launch overrides (as gv_search_tuning, unchecked)
 void set_tuning(int splits, int qpw, int cap);
 // smallest candidate-list capacity the scan accepts for kappa

@@ -3,6 +3,7 @@
 // full-dimension rerank (S4).  Algorithm 1 of the paper with the eager inner
 // product of Algorithm 4 and an exhaustive main step.
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <vector>
 
@@ -101,6 +102,11 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
 namespace {
 using namespace scan;
 
+// n counters to zero (a kernel rather than a memset node inside captured graphs)
+__global__ void k_zero_ints(int* __restrict__ p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 // seed[q] = -inf
 __global__ void k_seed_init(int64_t m, float* __restrict__ seed) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,9 +114,11 @@ __global__ void k_seed_init(int64_t m, float* __restrict__ seed) {
 }
 
 // after the dense scan: seed = kappa-th best score of the sample (one wavefront per query)
+constexpr int kDenseLds = 4096;  // sample rows a wavefront keeps in LDS
 __global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ dense, int64_t m, int64_t ns,
                                                       int kappa, float* __restrict__ seed) {
   __shared__ uint32_t hist[4][256];
+  __shared__ float s_row[4][kDenseLds];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t q = (int64_t)blockIdx.x * 4 + wave;
   if (q >= m) return;
@@ -120,8 +128,18 @@ __global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ 
   for (int o = 32; o > 0; o >>= 1) valid += __shfl_xor(valid, o);
   float tau = -INFINITY;
   if (valid >= kappa) {
-    auto load = [&](int i) { return make_key(row[i], (uint32_t)i); };
-    tau = key_score(wave_kth(load, (int)ns, kappa, hist[wave]));
+    if (ns <= kDenseLds) {
+      // the sample row once into this wavefront's LDS: the radix passes then
+      // read LDS instead of repeating global loads
+      float* r = s_row[wave];
+      for (int64_t i = lane; i < ns; i += 64) r[i] = row[i];
+      wave_sync();
+      auto load = [&](int i) { return make_key(r[i], (uint32_t)i); };
+      tau = key_score(wave_kth(load, (int)ns, kappa, hist[wave]));
+    } else {
+      auto load = [&](int i) { return make_key(row[i], (uint32_t)i); };
+      tau = key_score(wave_kth(load, (int)ns, kappa, hist[wave]));
+    }
   }
   if (lane == 0) seed[q] = fmaxf(seed[q], tau);
 }
@@ -211,19 +229,40 @@ __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf
   int kept = 0;
   for (int64_t w0 = 0; w0 < total; w0 += kSelWin - kappa) {
     const int wn = (int)std::min<int64_t>(total - w0, kSelWin - kappa);
-    for (int f = tid; f < wn; f += 256) {
-      const int g = (int)(w0 + f);
-      int lo = 0, hi = R - 1;  // list holding flat index g: last L with pre[L] <= g
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+    // each thread gathers up to kSelWin / 256 keys: every list position is found
+    // first, then all the loads are issued together (one memory latency per
+    // window instead of one per key)
+    constexpr int kPer = kSelWin / 256;
+    uint64_t kv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int f = tid + 256 * j;
+      kv[j] = 0;
+      if (f < wn) {
+        const int g = (int)(w0 + f);
+        int lo = 0, hi = R - 1;  // list holding flat index g: last L with pre[L] <= g
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        kv[j] = buf[(q * R + lo) * (int64_t)cap + (g - pre[lo])];
       }
-      uint64_t k = buf[(q * R + lo) * (int64_t)cap + (g - pre[lo])];
-      if (FINAL) {
-        const uint32_t row = 0xFFFFFFFFu - (uint32_t)k;
-        k = (k & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - (uint32_t)ids[row]);
+    }
+    if (FINAL) {  // re-key by original id (the ids are loaded together as well)
+      int32_t idv[kPer];
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int f = tid + 256 * j;
+        idv[j] = f < wn ? ids[0xFFFFFFFFu - (uint32_t)kv[j]] : 0;
       }
-      keys[kept + f] = k;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j)
+        kv[j] = (kv[j] & 0xFFFFFFFF00000000ull) | (uint64_t)(0xFFFFFFFFu - (uint32_t)idv[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int f = tid + 256 * j;
+      if (f < wn) keys[kept + f] = kv[j];
     }
     __syncthreads();
     const int n = kept + wn;
@@ -268,10 +307,15 @@ __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf
   }
 }
 
-Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C) {
+// whole_lists: one query block per workgroup (no tile ring), whose wavefronts
+// stage a whole list in a compaction -- for kappa beyond a ring shape's staging
+Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C, const Tuning& tu, bool whole_lists = false) {
   Shape sh;
-  const int qpw_override = tuned_qpw();
-  if (qpw_override > 0) {
+  const int qpw_override = tu.qpw;
+  if (whole_lists) {
+    sh.nb = m <= 32 ? 1 : 2;
+    sh.shared = true;
+  } else if (qpw_override > 0) {
     sh.nb = std::max(1, std::min(4, qpw_override / 32));
     sh.shared = m <= sh.nb * 32;
   } else if (m <= 32) {
@@ -291,7 +335,7 @@ Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C) {
   // rows, 2048 (two rounds of workgroups, which evens out ranges that hold many
   // survivors) otherwise; at least 4 tiles per range
   const int64_t waves = sh.shared ? 1024 : 2048;
-  int64_t R = tuned_splits() > 0 ? tuned_splits() : std::max<int64_t>(1, waves / sh.nqb);
+  int64_t R = tu.splits > 0 ? tu.splits : std::max<int64_t>(1, waves / sh.nqb);
   R = std::min<int64_t>(R, std::max<int64_t>(1, ntiles / 4));
   R = std::min<int64_t>(R, kMaxLists);
   if (sh.shared) {
@@ -306,6 +350,16 @@ Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C) {
   }
   sh.R = (int)R;
   return sh;
+}
+
+gv_status dispatch_fmt_queue(int fmt, int dp, const Shape& sh, int grid, const ScoreArgs* args, const int64_t* off,
+                             int ncoll, int* head, hipStream_t st) {
+  switch (fmt) {
+    case GV_FP32: return dispatch_scan_queue<GV_FP32>(dp, sh, grid, args, off, ncoll, head, st);
+    case GV_FP16: return dispatch_scan_queue<GV_FP16>(dp, sh, grid, args, off, ncoll, head, st);
+    case GV_BF16: return dispatch_scan_queue<GV_BF16>(dp, sh, grid, args, off, ncoll, head, st);
+    default: return dispatch_scan_queue<GV_FP8_E4M3>(dp, sh, grid, args, off, ncoll, head, st);
+  }
 }
 
 template <int MODE>
@@ -399,7 +453,8 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
     set_error("the scan reads at most the leading 256 stored coordinates (padded), and no more than the index stores");
     return GV_EUNSUPPORTED;
   }
-  p->cap = tuned_cap() > 0 ? tuned_cap() : kCap;
+  const Tuning tu = effective_tuning(fmt, p->dp, m, n);
+  p->cap = tu.cap > 0 ? tu.cap : kCap;
   if (p->cap <= kappa || p->cap > kCap) {
     set_error("candidate list capacity must lie in (kappa, 2048]");
     return GV_EINVAL;
@@ -412,16 +467,22 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
   p->Rmax = 1;
   for (size_t li = 0; li < p->levels.size(); ++li) {
     const int64_t s = p->levels[li];
-    const Shape sh = choose_shape(fmt, p->dp, m, (ntiles + s - 1) / s * kRows, C);
-    const ScanLimits lm = scan_limits(fmt, p->dp, sh);
+    const int64_t rows = (ntiles + s - 1) / s * kRows;
+    Shape sh = choose_shape(fmt, p->dp, m, rows, C, tu);
+    ScanLimits lm = scan_limits(fmt, p->dp, sh);
     const bool dense = p->has_dense && li == 0;  // the dense scan writes no lists
     if (!dense) {
-      p->Rmax = std::max(p->Rmax, sh.R);
       // a list is compacted once it holds more than lim keys and may then grow
       // by 32 keys per tile for U + 1 tiles before the next check: the staging
       // (CAPL) and the list (cap) must hold that, and a compaction to the kappa
       // best must leave room (lim > kappa)
-      const int lim = std::min(p->cap, lm.CAPL) - kRows * (lm.U + 1);
+      auto limit = [&](const ScanLimits& l) { return std::min(p->cap, l.CAPL) - kRows * (l.U + 1); };
+      if (limit(lm) <= kappa && !sh.shared) {  // a shape that stages whole lists
+        sh = choose_shape(fmt, p->dp, m, rows, C, tu, true);
+        lm = scan_limits(fmt, p->dp, sh);
+      }
+      p->Rmax = std::max(p->Rmax, sh.R);
+      const int lim = limit(lm);
       if (lim <= kappa) {
         set_error("kappa too large for the candidate lists of this launch shape (reduce kappa or raise the list cap)");
         return GV_EUNSUPPORTED;
@@ -458,8 +519,15 @@ struct LazyViews {
   int d, D, ds;
 };
 
+// Which part of the cascade run_scan issues: all of it; everything but the
+// full scan and its select (the full scan's arguments and shape are returned
+// instead, for a persistent launch that scans several searches); or only the
+// final select after such a launch.
+enum class Part { All, Prefix, Suffix };
+
 gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const void* qhat, const float* t, int64_t m,
-                   int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st, const LazyViews* lazy = nullptr) {
+                   int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st, const LazyViews* lazy = nullptr,
+                   Part part = Part::All, ScoreArgs* last_args = nullptr, Shape* last_shape = nullptr) {
   uint64_t* buf = (uint64_t*)(ws + p.off_buf);
   int32_t* cnt = (int32_t*)(ws + p.off_cnt);
   float* seed = p.has_dense ? (float*)(ws + p.off_seed) : nullptr;
@@ -498,7 +566,8 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
   };
 
   gv_status s = GV_OK;
-  if (p.has_dense) hipLaunchKernelGGL(k_seed_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, seed);
+  if (p.has_dense && part != Part::Suffix)
+    hipLaunchKernelGGL(k_seed_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, seed);
   for (size_t li = 0; li < p.levels.size() && s == GV_OK; ++li) {
     const Shape& sh = p.shapes[li];
     sh_cur = sh;
@@ -508,6 +577,22 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     args.nqb = (int)sh.nqb;
     args.stride = (int)p.levels[li];
     args.xcd_map = sh.xcd_map;
+    if (part == Part::Suffix && !last) continue;
+    if (part == Part::Prefix && last) {  // the full scan runs elsewhere, from these arguments
+      if (sh.R > p.Rmax || p.levels[li] != 1 || lazy) {
+        set_error("internal: candidate scratch smaller than the launch");
+        return GV_EDEVICE;
+      }
+      args.xcd_map = 0;  // a queue hands pieces to workgroups in any order
+      if (last_args) *last_args = args;
+      if (last_shape) *last_shape = sh;
+      break;
+    }
+    if (part == Part::Suffix) {
+      hipLaunchKernelGGL(k_select<true>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, p.cap, kappa, idx->ids,
+                         seed, cand_ids, cand_scores);
+      break;
+    }
     if (p.has_dense && li == 0) {
       s = dispatch(true);
       if (s == GV_OK)
@@ -674,6 +759,123 @@ gv_status search_lazy_impl(const gv_model* model, const gv_index* idx, const flo
   return s;
 }
 
+// ---------------------------------------------------------------------------- batched executor
+// Several searches (collections) as one launch sequence on `org`, for capture
+// into one graph: the projections and cascade levels of every search run as
+// branches on the side streams; then the full-database scans of all searches
+// run as persistent queue kernels, one per kernel instantiation, whose
+// workgroups pull (search, piece) items until every search's scan is done;
+// then the final selects and reranks run as branches again.  Each search has
+// its own workspace (its lists live from its cascade to its final select).
+gv_status batched_run(std::vector<BatchEntry>& e, int k, int kappa, hipStream_t org, hipStream_t* side, int nside,
+                      hipEvent_t fork, hipEvent_t* join, uint8_t* qmem, size_t qbytes, int n_cu,
+                      std::vector<uint8_t>* upload) {
+  const int ne = (int)e.size();
+  // classes: searches whose full scans share one kernel instantiation
+  struct Cls {
+    int fmt, dp, nb;
+    bool shared;
+    std::vector<int> members;
+  };
+  std::vector<Cls> cls;
+  std::vector<ScanPlan> plans(ne);
+  for (int i = 0; i < ne; ++i) {
+    GV_TRY(plan_scan(e[i].idx, e[i].m, kappa, &plans[i], e[i].plan.d_search));
+    const Shape& sh = plans[i].shapes.back();
+    const int fmt = e[i].idx->fmt, dp = plans[i].dp;
+    int c = -1;
+    for (int j = 0; j < (int)cls.size(); ++j)
+      if (cls[j].fmt == fmt && cls[j].dp == dp && cls[j].nb == sh.nb && cls[j].shared == sh.shared) c = j;
+    if (c < 0) {
+      cls.push_back(Cls{fmt, dp, sh.nb, sh.shared, {}});
+      c = (int)cls.size() - 1;
+    }
+    cls[c].members.push_back(i);
+  }
+  // queue memory: per class an argument array and a piece offset array, then
+  // one head counter per class
+  size_t o = 0;
+  std::vector<size_t> off_args(cls.size()), off_off(cls.size());
+  for (size_t c = 0; c < cls.size(); ++c) {
+    off_args[c] = o; o = align256(o + sizeof(ScoreArgs) * cls[c].members.size());
+    off_off[c] = o;  o = align256(o + sizeof(int64_t) * (cls[c].members.size() + 1));
+  }
+  const size_t off_heads = o;
+  o = align256(o + sizeof(int) * cls.size());
+  if (o > qbytes) {
+    set_error("internal: batched queue memory too small");
+    return GV_EDEVICE;
+  }
+  upload->assign(off_heads, 0);
+
+  // ---- branches: projections and cascade levels before the full scans
+  GV_HIP(hipEventRecord(fork, org));
+  for (int j = 0; j < nside; ++j) GV_HIP(hipStreamWaitEvent(side[j], fork, 0));
+  std::vector<ScoreArgs> last(ne);
+  std::vector<Shape> last_sh(ne);
+  for (int i = 0; i < ne; ++i) {
+    hipStream_t st = side[i % nside];
+    BatchEntry& b = e[i];
+    uint8_t* ws = b.ws;
+    float* t = (float*)(ws + b.plan.off_t);
+    float* qc = (float*)(ws + b.plan.off_qc);
+    void* qhat = ws + b.plan.off_qhat;
+    GV_TRY(project_impl(b.model, b.idx->fmt, b.Q, b.m, qc, t, qhat, st, b.plan.d_search));
+    GV_TRY(run_scan(b.idx, plans[i], ws + b.plan.off_scan, qhat, t, b.m, kappa, nullptr, nullptr, st, nullptr,
+                    Part::Prefix, &last[i], &last_sh[i]));
+  }
+  for (int j = 0; j < nside; ++j) {
+    GV_HIP(hipEventRecord(join[j], side[j]));
+    GV_HIP(hipStreamWaitEvent(org, join[j], 0));
+  }
+  // ---- the full scans: one persistent queue launch per class
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, org, (int*)(qmem + off_heads), (int)cls.size());
+  GV_HIP(hipGetLastError());
+  for (size_t c = 0; c < cls.size(); ++c) {
+    std::vector<int64_t> offs(cls[c].members.size() + 1, 0);
+    for (size_t j = 0; j < cls[c].members.size(); ++j) {
+      const int i = cls[c].members[j];
+      std::memcpy(upload->data() + off_args[c] + sizeof(ScoreArgs) * j, &last[i], sizeof(ScoreArgs));
+      offs[j + 1] = offs[j] + last_sh[i].grid;
+    }
+    std::memcpy(upload->data() + off_off[c], offs.data(), sizeof(int64_t) * offs.size());
+    const Shape& rep = last_sh[cls[c].members[0]];
+    const int occ = scan_limits(cls[c].fmt, cls[c].dp, rep).occupancy;
+    const int grid = (int)std::min<int64_t>(offs.back(), (int64_t)n_cu * occ);
+    GV_TRY(dispatch_fmt_queue(cls[c].fmt, cls[c].dp, rep, grid, (const ScoreArgs*)(qmem + off_args[c]),
+                              (const int64_t*)(qmem + off_off[c]), (int)cls[c].members.size(),
+                              (int*)(qmem + off_heads) + c, org));
+  }
+  // ---- branches: final selects and reranks
+  GV_HIP(hipEventRecord(fork, org));
+  for (int j = 0; j < nside; ++j) GV_HIP(hipStreamWaitEvent(side[j], fork, 0));
+  for (int i = 0; i < ne; ++i) {
+    hipStream_t st = side[i % nside];
+    BatchEntry& b = e[i];
+    uint8_t* ws = b.ws;
+    int32_t* cand = (int32_t*)(ws + b.plan.off_cand);
+    float* csc = (float*)(ws + b.plan.off_csc);
+    GV_TRY(run_scan(b.idx, plans[i], ws + b.plan.off_scan, nullptr, nullptr, b.m, kappa, cand, csc, st, nullptr,
+                    Part::Suffix));
+    if (b.plan.stored) {
+      float* qc = (float*)(ws + b.plan.off_qc);
+      GV_TRY(rerank_stored_impl(b.idx, qc, b.m, cand, kappa, k, b.out_ids, b.out_scores, st));
+    } else {
+      GV_TRY(rerank_impl(b.idx, b.Q, b.m, cand, kappa, k, b.out_ids, b.out_scores, st));
+    }
+  }
+  for (int j = 0; j < nside; ++j) {
+    GV_HIP(hipEventRecord(join[j], side[j]));
+    GV_HIP(hipStreamWaitEvent(org, join[j], 0));
+  }
+  return GV_OK;
+}
+
+size_t batched_queue_bytes(int n_entries) {
+  // at most one class per search: per class args, offsets and a head
+  return (size_t)n_entries * (align256(sizeof(scan::ScoreArgs)) + align256(sizeof(int64_t) * 2) + 512) + 4096;
+}
+
 // ============================================================================ S4
 namespace {
 
@@ -700,7 +902,10 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restri
     s_id[i] = 0x7fffffff;
   }
   __syncthreads();
-  // exact <q, x> with FP64 accumulation of exact FP32 x FP32 products
+  // exact <q, x> with FP64 accumulation of exact FP32 x FP32 products; each
+  // lane loads its part of four candidate rows with every load in flight before
+  // the first use (the rows are gathered: one memory latency per group of four)
+  const bool vec = (D % 4) == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)Q % 16) == 0;
   for (int c0 = wave * 4; c0 < kappa; c0 += W * 4) {
     int32_t id[4];
     bool ok[4];
@@ -712,10 +917,47 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restri
       x[u] = X + (ok[u] ? (int64_t)id[u] : 0) * D;
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = lane; j < D; j += 64) {
-      const double qj = (double)qv[j];
+    int j0 = 0;
+    if (vec) {
+      constexpr int kChunk = 4;  // float4 groups per lane per pass: 1024 coordinates of a row
+      for (; j0 + 256 * kChunk <= D; j0 += 256 * kChunk) {
+        float4 xv[4][kChunk], qq[kChunk];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += (double)x[u][j] * qj;
+        for (int c = 0; c < kChunk; ++c) {
+          const int j = j0 + 4 * (lane + 64 * c);
+          qq[c] = *(const float4*)(qv + j);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) xv[u][c] = *(const float4*)(x[u] + j);
+        }
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            acc[u] += (double)xv[u][c].x * (double)qq[c].x;
+            acc[u] += (double)xv[u][c].y * (double)qq[c].y;
+            acc[u] += (double)xv[u][c].z * (double)qq[c].z;
+            acc[u] += (double)xv[u][c].w * (double)qq[c].w;
+          }
+      }
+      for (int j = j0 + 4 * lane; j + 4 <= D; j += 256) {
+        const float4 qq = *(const float4*)(qv + j);
+        float4 xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = *(const float4*)(x[u] + j);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc[u] += (double)xv[u].x * (double)qq.x;
+          acc[u] += (double)xv[u].y * (double)qq.y;
+          acc[u] += (double)xv[u].z * (double)qq.z;
+          acc[u] += (double)xv[u].w * (double)qq.w;
+        }
+      }
+    } else {
+      for (int j = lane; j < D; j += 64) {
+        const double qj = (double)qv[j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += (double)x[u][j] * qj;
+      }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {

@@ -131,6 +131,28 @@ struct WaveSmem {
   uint64_t idk[CAPL];  // compaction: the list's keys
 };
 
+// ---- LDS of one workgroup: four wavefronts' staging (WaveSmem) and the tile
+// ring.  A CU has 160 KiB, so two workgroups per CU take at most 80 KiB each.
+constexpr int wave_smem_bytes(int qw, int capl) { return (qw * 4 + 256 * 4 + 4 + 7) / 8 * 8 + 8 * capl; }
+constexpr int lds_budget(int occ) { return 160 * 1024 / occ - 256; }  // some room for the queue kernel's own words
+template <int FMT, int KS>
+constexpr int ring_tile_bytes() { return KS * 64 * MfmaOp<FMT>::EPL * MfmaOp<FMT>::EB; }
+// tiles of a ring shared by two workgroups per CU: four where they fit beside a
+// staging of half a list, else three (the fewest the pipeline needs)
+template <int FMT, int KS, int NB>
+constexpr int ring_tiles_two_per_cu() {
+  return 4 * wave_smem_bytes(32 * NB, kCap / 2) + 4 * ring_tile_bytes<FMT, KS>() <= lds_budget(2) ? 4 : 3;
+}
+// keys a compaction can stage: the whole list with one workgroup per CU and no
+// ring; else half a list, or 768 keys where a ring of the longest tiles leaves
+// no room for half a list
+template <int FMT, int KS, int NB, int OCC, bool WGT, int PL>
+constexpr int staging_keys() {
+  if (!(OCC >= 2 || WGT)) return kCap;
+  const int ring = WGT ? PL * ring_tile_bytes<FMT, KS>() : 16;
+  return 4 * wave_smem_bytes(32 * NB, kCap / 2) + ring <= lds_budget(OCC) ? kCap / 2 : 768;
+}
+
 // Reduce the list L of n keys (n > keep), keyed (score desc, stored row asc),
 // so that it still holds the `keep` best by (score desc, original id asc).
 // Usual case: every key whose score reaches the keep-th best score stays (ties
@@ -230,6 +252,14 @@ __device__ __forceinline__ void block_barrier() {
   __asm__ volatile("" ::: "memory");
 }
 
+// k-step operand sets held in registers on the LDS ring: the smallest divisor
+// of the tile's k-steps that is at least 4 (all of them below 4)
+constexpr int window_steps(int ks) {
+  for (int w = 4; w < ks; ++w)
+    if (ks % w == 0) return w;
+  return ks;
+}
+
 // compile-time unrolled loop: f(std::integral_constant<int, i>) for i in [I, N)
 template <int I, int N>
 struct Unroll {
@@ -296,9 +326,12 @@ __device__ inline float lazy_view(const double* __restrict__ A, const float* __r
   return t;
 }
 
+// The scan of one workgroup-sized piece b of a launch (four work items), shared
+// by the one-search kernel (b = blockIdx.x) and the persistent kernel that
+// pulls pieces of several searches from a queue.
 template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC, bool FULL, bool WGT, int PL,
-          bool LAZY = false>
-__global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
+          bool LAZY>
+__device__ __forceinline__ void scan_body(const ScoreArgs& a, const int b_item) {
   using Op = MfmaOp<FMT>;
   using S = typename Op::S;
   using T = typename Op::T;
@@ -311,8 +344,13 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
 
   // two workgroups per CU, or an LDS tile ring, need the smaller compaction staging
   // (KernelCfg states the same constants for the host-side plan checks)
-  constexpr int CAPL = (OCC >= 2 || WGT) ? kCap / 2 : kCap;
+  constexpr int CAPL = staging_keys<FMT, KS, NB, OCC, WGT, PL>();
   static_assert(CAPL - kRows * (U + 1) >= 256 + kRows, "the staging must hold kappa <= 256 plus a tile");
+  static_assert(sizeof(WaveSmem<QW, CAPL>) == wave_smem_bytes(QW, CAPL), "staging size as planned");
+  static_assert(TB == ring_tile_bytes<FMT, KS>(), "tile size as planned");
+  static_assert(4 * sizeof(WaveSmem<QW, CAPL>) + (WGT ? PL * TB : 16) + (LAZY ? 4 * QW * KS * 16 * 2 + 16 * QW : 32) <=
+                    lds_budget(OCC),
+                "the workgroup's LDS must allow OCC workgroups per CU");
   __shared__ WaveSmem<QW, CAPL> s_wave[4];
   __shared__ __attribute__((aligned(16))) uint8_t s_ring[WGT ? PL * TB : 16];
   // lazy views: per wavefront, its queries' FP16 views of the visited cluster
@@ -326,7 +364,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   // ---- workgroup -> four (query block, range) work items
   int qb, r;
   {
-    const int b = blockIdx.x;
+    const int b = b_item;
     if (SHARED) {
       const int rgroups = a.R / 4;
       qb = b / rgroups;
@@ -549,11 +587,27 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
 #pragma unroll
       for (int s = 0; s < KS; ++s) dst[s] = *(const S*)(p + s * kblock);
     };
+    // LDS tile ring: the k-step operands pass through a window of LW register
+    // sets.  K-step s of tile t sits in win[s % LW]; once consumed, its set
+    // takes k-step s + LW, of tile t or, past the tile's end, k-step
+    // s + LW - KS of tile t + 1 -- the same set since LW divides KS.  (LW sets
+    // instead of a whole tile keep two wavefronts per SIMD within 256
+    // registers; LW k-steps of matrix-core work cover an LDS read.)
+    constexpr int LW = WGT ? window_steps(KS) : KS;
+    static_assert(KS % LW == 0, "the window must divide the tile's k-steps");
+    auto refill = [&](S (&win)[LW], auto stc, const uint8_t* cur_p, const uint8_t* nxt_p) __attribute__((always_inline)) {
+      constexpr int st_ = decltype(stc)::value;
+      constexpr int nx = st_ + LW;
+      if constexpr (nx < KS) win[st_ % LW] = *(const S*)(cur_p + nx * kblock_c);
+      else win[st_ % LW] = *(const S*)(nxt_p + (nx - KS) * kblock_c);
+    };
     // matrix-core chain of one tile with the maxima of the previous tile's
     // scores (Pv) computed between its steps: the vector ALU work runs while
-    // the matrix core is busy instead of after it
-    auto mma_tile_max = [&](S (&src)[KS], f32x16 (&A)[NB], const f32x16 (&Pv)[NB], float (&mx)[NB],
-                            const uint8_t* refill) __attribute__((always_inline)) {
+    // the matrix core is busy instead of after it.  src: the tile's operands
+    // (register ring), or the LDS ring's window with the tile's and the next
+    // tile's slots (cur_p, nxt_p)
+    auto mma_tile_max = [&](auto& src, f32x16 (&A)[NB], const f32x16 (&Pv)[NB], float (&mx)[NB],
+                            const uint8_t* cur_p, const uint8_t* nxt_p) __attribute__((always_inline)) {
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
         constexpr int nb = decltype(nbc)::value;
         A[nb] = f32x16{0};
@@ -561,13 +615,12 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
       });
       Unroll<0, KS>::run([&](auto sc) __attribute__((always_inline)) {
         constexpr int st_ = decltype(sc)::value;
-        const T av = Op::cvt(src[st_]);
+        const T av = Op::cvt(src[WGT ? st_ % LW : st_]);
         Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
           constexpr int nb = decltype(nbc)::value;
           A[nb] = Op::mma(av, bq[nb][st_], A[nb]);
         });
-        // this k-step's operand is consumed: its registers take the next tile's
-        if constexpr (WGT) src[st_] = *(const S*)(refill + st_ * kblock_c);
+        if constexpr (WGT) refill(src, sc, cur_p, nxt_p);
         constexpr int j0 = 1 + st_ * 15 / KS, j1 = 1 + (st_ + 1) * 15 / KS;
         Unroll<j0, j1>::run([&](auto jc) __attribute__((always_inline)) {
           constexpr int j = decltype(jc)::value;
@@ -596,6 +649,20 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
         });
       }
     };
+    // the same through the LDS ring's window
+    auto mma_tile_win = [&](S (&win)[LW], f32x16 (&A)[NB], const uint8_t* cur_p, const uint8_t* nxt_p)
+        __attribute__((always_inline)) {
+      Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) { A[decltype(nbc)::value] = f32x16{0}; });
+      Unroll<0, KS>::run([&](auto sc) __attribute__((always_inline)) {
+        constexpr int st_ = decltype(sc)::value;
+        const T av = Op::cvt(win[st_ % LW]);
+        Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
+          constexpr int nb = decltype(nbc)::value;
+          A[nb] = Op::mma(av, bq[nb][st_], A[nb]);
+        });
+        refill(win, sc, cur_p, nxt_p);
+      });
+    };
 
     if constexpr (WGT) {
       // ---- tiles shared by the workgroup through an LDS ring of PL tiles.  Each
@@ -606,8 +673,10 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
       // in order, so "at most N outstanding", N = the copies issued after the
       // tile's, is met only once the tile's copies have landed.  Survivor
       // stores issued in between count too: the wait is then longer than
-      // needed, never shorter.  The reads of tile t + 1 go out before the
-      // matrix-core chain of tile t and land while it runs.
+      // needed, never shorter.  Each k-step's operands are read from the ring
+      // LW k-steps before their matrix-core ops, so a tile's slot is read while
+      // that tile and the one before it are scored; a wavefront has received
+      // every read of a tile before it reaches the barrier after that tile.
       static_assert(TB % 1024 == 0, "tiles are copied in 1 KiB chunks");
       constexpr int NCH = TB / 1024;
       constexpr int SH_HI = (NCH + 3) / 4, SH_LO = NCH / 4;
@@ -637,10 +706,11 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
       Unroll<0, PL - 1>::run([&](auto pc) __attribute__((always_inline)) { issue(v0 + decltype(pc)::value); });
       arrive(std::integral_constant<int, PL - 2>{});
       f32x16 acc0[NB], acc1[NB];
-      S cur[KS];
+      S win[LW];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) cur[s] = *(const S*)(ring_lane + s * kblock_c);
+      for (int s = 0; s < LW; ++s) win[s] = *(const S*)(ring_lane + s * kblock_c);
       int slot_rd = 1;  // ring slot of the next tile
+      int slot_cur = 0;  // ring slot of the tile being scored
       for (int64_t vb = v0; vb < v1; vb += 2) {
         Unroll<0, 2>::run([&](auto uc) __attribute__((always_inline)) {
           constexpr int u = decltype(uc)::value;
@@ -653,18 +723,19 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
             arrive(std::integral_constant<int, PL - 3>{});
             issue(vt + PL - 1);
           }
-          // the matrix-core chain of tile vt refills each k-step's operand from
-          // tile vt + 1 (after the last tile the reads are discarded)
+          // the matrix-core chain of tile vt reads the rest of tile vt and the
+          // first LW k-steps of tile vt + 1 (after the last tile those reads
+          // are discarded)
+          const uint8_t* curp = ring_lane + slot_cur * TB;
           const uint8_t* nxt = ring_lane + slot_rd * TB;
+          slot_cur = slot_rd;
           slot_rd = slot_rd + 1 == PL ? 0 : slot_rd + 1;
           if constexpr (MODE == kFilter) {
             float mx[NB];
-            if constexpr (u & 1) mma_tile_max(cur, acc1, acc0, mx, nxt); else mma_tile_max(cur, acc0, acc1, mx, nxt);
+            if constexpr (u & 1) mma_tile_max(win, acc1, acc0, mx, curp, nxt); else mma_tile_max(win, acc0, acc1, mx, curp, nxt);
             if constexpr (u & 1) filter(acc0, vt - 1, real_end, mx, vt > v0); else filter(acc1, vt - 1, real_end, mx, vt > v0);
           } else {
-            if constexpr (u & 1) mma_tile(cur, acc1); else mma_tile(cur, acc0);
-#pragma unroll
-            for (int s = 0; s < KS; ++s) cur[s] = *(const S*)(nxt + s * kblock_c);
+            if constexpr (u & 1) mma_tile_win(win, acc1, curp, nxt); else mma_tile_win(win, acc0, curp, nxt);
             if (vt > v0) {
               if constexpr (u & 1) epilogue(acc0, vt - 1, real_end); else epilogue(acc1, vt - 1, real_end);
             }
@@ -692,7 +763,7 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
           if constexpr (DEFER && MODE == kFilter) {
             // matrix core on tile vt, beside it the maxima of tile vt - 1, then its filter
             float mx[NB];
-            if constexpr (u & 1) mma_tile_max(ring[u % P], acc1, acc0, mx, nullptr); else mma_tile_max(ring[u % P], acc0, acc1, mx, nullptr);
+            if constexpr (u & 1) mma_tile_max(ring[u % P], acc1, acc0, mx, nullptr, nullptr); else mma_tile_max(ring[u % P], acc0, acc1, mx, nullptr, nullptr);
             const bool valid = (u > 0 || vt > v0) && vt - 1 < v1;
             if constexpr (u & 1) filter(acc0, vt - 1, real_end, mx, valid); else filter(acc1, vt - 1, real_end, mx, valid);
           } else if constexpr (DEFER) {
@@ -725,6 +796,36 @@ __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
         if (q < a.m) a.cnt_out[q * a.R + r] = cnt[nb];
       });
     }
+  }
+}
+
+template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC, bool FULL, bool WGT, int PL,
+          bool LAZY = false>
+__global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
+  scan_body<FMT, KS, NB, SHARED, MODE, P, DEFER, OCC, FULL, WGT, PL, LAZY>(a, blockIdx.x);
+}
+
+// Persistent form: workgroups pull pieces (c, b) -- search c, piece b of its
+// launch grid -- from one queue over several searches that share this
+// instantiation, until the queue is drained.  off[c] is the first queue index
+// of search c (off[ncoll] = all pieces); *head starts at 0.  Every workgroup
+// leaves once the head passes the end, so the grid drains.
+template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int OCC, bool FULL, bool WGT, int PL>
+__global__ __launch_bounds__(256, OCC) void k_scan_queue(const ScoreArgs* __restrict__ args,
+                                                         const int64_t* __restrict__ off, int ncoll,
+                                                         int* __restrict__ head) {
+  __shared__ int s_item;
+  const int64_t total = off[ncoll];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
+    __syncthreads();
+    const int64_t it = __builtin_amdgcn_readfirstlane(s_item);  // uniform: the search's arguments load as scalars
+    __syncthreads();  // every wave has the item before thread 0 takes the next one
+    if (it >= total) break;
+    int c = 0;
+    while (c + 1 < ncoll && off[c + 1] <= it) ++c;
+    const ScoreArgs a = args[c];
+    scan_body<FMT, KS, NB, SHARED, MODE, P, DEFER, OCC, FULL, WGT, PL, false>(a, (int)(it - off[c]));
   }
 }
 
@@ -770,20 +871,21 @@ struct RingCfg {
 // and by the host-side plan checks (scan_limits).  With two query blocks per
 // wavefront on the LDS ring, two workgroups share a CU (two wavefronts per SIMD,
 // 256 registers each): one wavefront's filter, barrier and LDS waits overlap the
-// other's matrix-core chain.  Its ring is four tiles deep and its compaction
-// staging 1024 keys, so two workgroups fit the LDS (tiles up to 10 KiB).
+// other's matrix-core chain.  Two such workgroups must fit the LDS: the ring is
+// four tiles deep and the compaction staging 1024 keys up to 10 KiB tiles; 12
+// KiB tiles take a ring of three; 16 KiB tiles a ring of three and 768 keys.
 template <int FMT, int KS, int NB, bool SHARED>
 struct KernelCfg {
   using Cfg = ScanCfg<FMT, KS, NB>;
   static constexpr bool W = !SHARED && RingCfg<FMT, KS>::ok;  // workgroup-shared LDS tile ring
   static constexpr int OC = (W && NB == 2) ? 2 : 1;             // workgroups per CU
-  static constexpr int PL = W ? (OC == 2 ? 4 : RingCfg<FMT, KS>::PL) : 1;
+  static constexpr int PL = W ? (OC == 2 ? ring_tiles_two_per_cu<FMT, KS, NB>() : RingCfg<FMT, KS>::PL) : 1;
   static constexpr bool DEF = W || Cfg::defer;
   static constexpr int P = Cfg::P;
   // tiles between two overflow checks of a list (the kernel's unrolled steps)
   static constexpr int U = W ? 2 : (DEF ? 2 * P : P);
   // keys a compaction can stage in the wavefront's LDS
-  static constexpr int CAPL = (OC >= 2 || W) ? kCap / 2 : kCap;
+  static constexpr int CAPL = staging_keys<FMT, KS, NB, OC, W, PL>();
 };
 
 template <int FMT, int KS, int NB, bool SHARED, int MODE>
@@ -857,6 +959,51 @@ void launch_score(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   }
 }
 
+template <int FMT, int KS, int NB, bool SHARED>
+void launch_queue_one(int grid, const ScoreArgs* args, const int64_t* off, int ncoll, int* head, hipStream_t st) {
+  using K = KernelCfg<FMT, KS, NB, SHARED>;
+  hipLaunchKernelGGL((k_scan_queue<FMT, KS, NB, SHARED, kFilter, K::P, K::DEF, K::OC, true, K::W, K::PL>),
+                     dim3(grid), dim3(256), 0, st, args, off, ncoll, head);
+}
+
+// the full-scan instantiation launch_score picks for a shape, as a queue kernel
+template <int FMT, int KS>
+void launch_queue(const Shape& sh, int grid, const ScoreArgs* args, const int64_t* off, int ncoll, int* head,
+                  hipStream_t st) {
+  if constexpr (FMT == GV_FP32) {
+    if (sh.shared) launch_queue_one<FMT, KS, 1, true>(grid, args, off, ncoll, head, st);
+    else launch_queue_one<FMT, KS, 1, false>(grid, args, off, ncoll, head, st);
+  } else {
+    if (sh.shared && sh.nb == 1) launch_queue_one<FMT, KS, 1, true>(grid, args, off, ncoll, head, st);
+    else if (sh.shared) launch_queue_one<FMT, KS, 2, true>(grid, args, off, ncoll, head, st);
+    else if constexpr (KS <= 10) {
+      if (sh.nb == 4) launch_queue_one<FMT, KS, 4, false>(grid, args, off, ncoll, head, st);
+      else launch_queue_one<FMT, KS, 2, false>(grid, args, off, ncoll, head, st);
+    } else {
+      launch_queue_one<FMT, KS, 2, false>(grid, args, off, ncoll, head, st);
+    }
+  }
+}
+
+template <int FMT>
+gv_status dispatch_queue_ks(int dp, const Shape& sh, int grid, const ScoreArgs* args, const int64_t* off, int ncoll,
+                            int* head, hipStream_t st) {
+  constexpr int km = MfmaOp<FMT>::KM;
+  switch (dp / km) {
+    case 32 / km: launch_queue<FMT, 32 / km>(sh, grid, args, off, ncoll, head, st); break;
+    case 64 / km: launch_queue<FMT, 64 / km>(sh, grid, args, off, ncoll, head, st); break;
+    case 128 / km: launch_queue<FMT, 128 / km>(sh, grid, args, off, ncoll, head, st); break;
+    case 160 / km: launch_queue<FMT, 160 / km>(sh, grid, args, off, ncoll, head, st); break;
+    case 192 / km: launch_queue<FMT, 192 / km>(sh, grid, args, off, ncoll, head, st); break;
+    case 256 / km: launch_queue<FMT, 256 / km>(sh, grid, args, off, ncoll, head, st); break;
+    default:
+      set_error("reduced dimension above 256 is not supported by the scoring kernel");
+      return GV_EUNSUPPORTED;
+  }
+  GV_HIP(hipGetLastError());
+  return GV_OK;
+}
+
 template <int FMT, int MODE>
 gv_status dispatch_ks(int dp, const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   constexpr int km = MfmaOp<FMT>::KM;
@@ -883,5 +1030,10 @@ gv_status dispatch_scan(int dp, const scan::Shape& sh, const scan::ScoreArgs& ar
 // the lazy variant (scan_fp16.hip)
 template <int MODE>
 gv_status dispatch_scan_lazy(const scan::Shape& sh, const scan::ScoreArgs& args, hipStream_t st);
+// the persistent full scan over several searches (grid workgroups pull the
+// pieces of the searches' argument blocks args[0, ncoll) from the queue *head)
+template <int FMT>
+gv_status dispatch_scan_queue(int dp, const scan::Shape& sh, int grid, const scan::ScoreArgs* args,
+                              const int64_t* off, int ncoll, int* head, hipStream_t st);
 
 }  // namespace gv

@@ -152,3 +152,28 @@ def test_batched_errors(gv, collections):
         gv.search_batched(models, indexes, Qs, 10, 100000)  # kappa > n
     with pytest.raises(ValueError):
         gv.search_batched(models[:2], indexes, Qs, 10, 40)
+
+
+def test_autotune_keeps_results_and_feeds_the_table(gv, collections):
+    """The autotuner times launch shapes and stores the fastest for the shape class;
+    searches (single and batched) then use it, and their results stay bit-equal to
+    the untuned ones (the launch shape never changes a result)."""
+    k, kappa = 10, 40
+    c, md, ix, Q = collections[4]
+    gv.tuning_table_clear()
+    ref = gv.search(md, ix, Q, k, kappa)
+    r = gv.autotune(md, ix, Q, k, kappa, reps=2)
+    _say(f"[autotune] {r}")
+    assert r["candidates"] >= 2 and r["ms"] <= r["ms_automatic"] + 1e-9
+    assert gv.tuning_lookup("bf16", ix.d_pad, Q.shape[0], ix.rows) == (r["splits"], r["qpw"], r["cap"])
+    got = gv.search(md, ix, Q, k, kappa)
+    torch.cuda.synchronize()
+    assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+    models = [b[1] for b in collections]
+    indexes = [b[2] for b in collections]
+    Qs = [b[3] for b in collections]
+    out = gv.search_batched(models, indexes, Qs, k, kappa)
+    torch.cuda.synchronize()
+    assert torch.equal(out[4][0], ref[0]) and torch.equal(out[4][1], ref[1])
+    gv.batch_release()
+    gv.tuning_table_clear()

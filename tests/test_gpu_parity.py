@@ -46,6 +46,9 @@ CASES = {
     # cascade levels below the full scan (every 256th tile dense, every 16th filtered):
     # the sampled-level and full-scan kernels the benchmark launches at m <= 64
     "d160-n420k": (107, 256, 8, 420_000, 4_000, 160, 8, 64, 200),
+    # the longest reduced rows (12 and 16 KiB tiles in 16-bit storage)
+    "d192-C8": (108, 384, 8, 24_000, 4_000, 192, 8, 130, 200),
+    "d256-C8": (109, 512, 8, 24_000, 4_000, 256, 8, 130, 200),
 }
 
 
@@ -378,6 +381,69 @@ def test_long_lists_tile_ring(gv, fmt):
         tol_id = np.empty(n); tol_id[oi.ids] = tol[qi]
         flips += check_topk_sets(c2[qi], d2[qi], by_id, tol_id, kappa, f"q{qi}")
     assert flips <= max(1, m // 50)
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp8"])
+@pytest.mark.parametrize("case", ["d192-C8", "d256-C8"])
+def test_tile_ring_longest_rows(gv, case, fmt):
+    """Reduced lengths 192 and 256 with many queries: the workgroup-shared tile
+    ring at two workgroups per CU (a ring of three 12 KiB tiles; three 16 KiB tiles
+    beside a 768-key compaction staging).  Candidates match the oracle, at the
+    automatic shape and with one row range per query (long lists compacted at the
+    staging's limit), and both shapes give the same lists."""
+    _, _, _, _, _, _, _, m, _ = CASES[case]
+    _say(f"[ring] {case} {fmt} m{m}")
+    X, Q, om, oi, model, idx, Xd, kappa = _search_setup(gv, case, fmt, m)
+    if not np.array_equal(idx.export()["tags"], oi.tags):
+        pytest.skip("near-tie tag")
+    Qd = dev(Q)
+    _, t, qhat = gv.project(model, fmt, Qd, want_qc=False)
+    c1, d1 = gv.score_topk(idx, qhat, t, kappa)
+    gv.search_tuning(splits=1, qpw=0, cap=0)
+    try:
+        c2, d2 = gv.score_topk(idx, qhat, t, kappa)
+    finally:
+        gv.search_tuning(0, 0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(c1, c2) and torch.equal(d1, d2)
+    out = G.search(oi, om.A, Q, 10, kappa)
+    tol = reduced_score_tolerance(out, oi, idx.d_pad)
+    n = X.shape[0]
+    c1 = c1.cpu().numpy(); d1 = d1.cpu().numpy()
+    flips = 0
+    for qi in range(m):
+        by_id = np.empty(n); by_id[oi.ids] = out["scores"][qi]
+        tol_id = np.empty(n); tol_id[oi.ids] = tol[qi]
+        flips += check_topk_sets(c1[qi], d1[qi], by_id, tol_id, kappa, f"q{qi}")
+    assert flips <= max(2, m // 20)
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp32"])
+def test_kappa_beyond_ring_staging(gv, fmt):
+    """kappa = 1000 with 130 queries: more than a tile-ring workgroup's compaction
+    staging can keep, so the plan takes shared query blocks whose wavefronts stage
+    whole lists.  The candidates match the oracle and the end-to-end search is
+    proven against it."""
+    m, kappa = 130, 1000
+    _say(f"[kappa {kappa}] {fmt} m{m}")
+    X, Q, om, oi, model, idx, Xd, _ = _search_setup(gv, "d160-C8", fmt, m)
+    if not np.array_equal(idx.export()["tags"], oi.tags):
+        pytest.skip("near-tie tag")
+    Qd = dev(Q)
+    _, t, qhat = gv.project(model, fmt, Qd, want_qc=False)
+    cid, csc = gv.score_topk(idx, qhat, t, kappa)
+    torch.cuda.synchronize()
+    out = G.search(oi, om.A, Q, 10, kappa)
+    tol = reduced_score_tolerance(out, oi, idx.d_pad)
+    n = X.shape[0]
+    cid = cid.cpu().numpy(); csc = csc.cpu().numpy()
+    flips = 0
+    for qi in range(m):
+        by_id = np.empty(n); by_id[oi.ids] = out["scores"][qi]
+        tol_id = np.empty(n); tol_id[oi.ids] = tol[qi]
+        flips += check_topk_sets(cid[qi], csc[qi], by_id, tol_id, kappa, f"q{qi}")
+    assert flips <= max(2, m // 20)
+    verify_search(gv, model, idx, X, Q, oi, out, kappa, 10, fmt, f"kappa {kappa} {fmt}")
 
 
 @pytest.mark.parametrize("fmt", ["fp16", "fp8"])

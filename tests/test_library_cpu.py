@@ -165,6 +165,7 @@ def test_scan_plan_invariants():
       * a list checked every U tiles, compacted above list_limit, never outgrows
         its slots or the wavefront's LDS staging: list_limit + 32 (U + 1) <= min(cap, staging);
       * a compaction to the kappa best leaves room: list_limit > kappa;
+      * without overrides every kappa <= 1024 is served for batches up to 4096;
       * the grid covers every (query block, range) work item exactly;
       * the cascade's dense sample comes first, the full scan last, strides nested."""
     import paper_2410_22347_amd as gv
@@ -186,6 +187,9 @@ def test_scan_plan_invariants():
                                     st, lv, keys, ws = _plan(lib, n, n_pad, C, fmt, d, 0, m, kappa)
                                     if st != 0:
                                         assert st in (-6, -1), st
+                                        # the automatic shapes serve every kappa <= 1024 for
+                                        # batches whose lists fit the 32-bit slot space
+                                        assert (splits, qpw, cap) != (0, 0, 0) or m > 4096, (n, C, d, fmt, m, kappa)
                                         refused += 1
                                         continue
                                     checked += 1
@@ -213,3 +217,31 @@ def test_scan_plan_invariants():
         finally:
             lib.gv_search_tuning(0, 0, 0)
     assert checked > 10_000 and refused < checked
+
+
+def test_tuning_table_file_round_trip(tmp_path):
+    """The autotuner's table as a text file: lines written by hand load, their
+    shape classes look up (batch and size classes as documented), a malformed line
+    is refused, and the saved table reads back the same."""
+    import paper_2410_22347_amd as gv
+    gv.tuning_table_clear()
+    p = tmp_path / "tune.txt"
+    p.write_text("# fmt d_pad batch_class size_class splits qpw cap ms\n"
+                 "1 160 5 23 64 64 0 14.5\n"
+                 "2 64 0 20 0 32 768 0.5\n")
+    gv.tuning_table_load(str(p))
+    assert gv.tuning_lookup("fp16", 160, 4096, 10_000_000) == (64, 64, 0)   # 2^23 <= 1e7 < 2^24
+    assert gv.tuning_lookup("fp16", 160, 4000, 9_000_000) == (64, 64, 0)    # same classes
+    assert gv.tuning_lookup("fp16", 160, 5000, 10_000_000) is None          # batch class 6
+    assert gv.tuning_lookup("bf16", 64, 1, 1_500_000) == (0, 32, 768)
+    q = tmp_path / "again.txt"
+    gv.tuning_table_save(str(q))
+    gv.tuning_table_clear()
+    assert gv.tuning_lookup("bf16", 64, 1, 1_500_000) is None
+    gv.tuning_table_load(str(q))
+    assert gv.tuning_lookup("fp16", 160, 4096, 10_000_000) == (64, 64, 0)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1 160 5 23 64 48 0 1.0\n")                              # qpw 48 is not a shape
+    with pytest.raises(gv.GleanVecError):
+        gv.tuning_table_load(str(bad))
+    gv.tuning_table_clear()
