@@ -113,34 +113,75 @@ __global__ void k_seed_init(int64_t m, float* __restrict__ seed) {
   if (q < m) seed[q] = -INFINITY;
 }
 
-// after the dense scan: seed = kappa-th best score of the sample (one wavefront per query)
-constexpr int kDenseLds = 4096;  // sample rows a wavefront keeps in LDS
+// after the dense scan: seed = a lower bound of the kappa-th best score of the
+// sample (one wavefront per query).  Any such bound is a valid seed (at least
+// kappa rows of the next level reach it); this one is the smallest score whose
+// order key shares the top 22 bits of the kappa-th best's key (within 2^-13 of
+// it, relatively), found from two 11-bit histograms: two passes over the row
+// instead of the four or more of an exact radix select.
+constexpr int kBoundBins = 2048;
 __global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ dense, int64_t m, int64_t ns,
                                                       int kappa, float* __restrict__ seed) {
-  __shared__ uint32_t hist[4][256];
-  __shared__ float s_row[4][kDenseLds];
+  __shared__ uint32_t hist[4][kBoundBins];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t q = (int64_t)blockIdx.x * 4 + wave;
   if (q >= m) return;
   const float* row = dense + q * ns;
+  uint32_t* h = hist[wave];
+  constexpr int kUn = 8;  // loads in flight per lane
   int valid = 0;
-  for (int64_t i = lane; i < ns; i += 64) valid += row[i] != -INFINITY;
-  for (int o = 32; o > 0; o >>= 1) valid += __shfl_xor(valid, o);
-  float tau = -INFINITY;
-  if (valid >= kappa) {
-    if (ns <= kDenseLds) {
-      // the sample row once into this wavefront's LDS: the radix passes then
-      // read LDS instead of repeating global loads
-      float* r = s_row[wave];
-      for (int64_t i = lane; i < ns; i += 64) r[i] = row[i];
-      wave_sync();
-      auto load = [&](int i) { return make_key(r[i], (uint32_t)i); };
-      tau = key_score(wave_kth(load, (int)ns, kappa, hist[wave]));
-    } else {
-      auto load = [&](int i) { return make_key(row[i], (uint32_t)i); };
-      tau = key_score(wave_kth(load, (int)ns, kappa, hist[wave]));
+  uint32_t prefix = 0, need = (uint32_t)kappa;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int shift = pass == 0 ? 21 : 10;
+    const uint32_t mask = pass == 0 ? 0u : 0xFFE00000u;
+    for (int b = lane; b < kBoundBins; b += 64) h[b] = 0;
+    wave_sync();
+    for (int64_t i0 = lane; i0 < ns; i0 += 64 * kUn) {
+      float v[kUn];
+#pragma unroll
+      for (int u = 0; u < kUn; ++u) v[u] = i0 + 64 * u < ns ? row[i0 + 64 * u] : -INFINITY;
+#pragma unroll
+      for (int u = 0; u < kUn; ++u) {
+        if (pass == 0) valid += v[u] != -INFINITY;
+        const uint32_t k = order_f32(v[u]);
+        if (i0 + 64 * u < ns && (k & mask) == prefix) atomicAdd(&h[(k >> shift) & (kBoundBins - 1)], 1u);
+      }
     }
+    if (pass == 0) {
+      for (int o = 32; o > 0; o >>= 1) valid += __shfl_xor(valid, o);
+      if (valid < kappa) return;  // fewer than kappa scores: no bound
+    }
+    wave_sync();
+    // lane l owns bins [32 l, 32 l + 32); keys in all higher bins, by a suffix scan
+    uint32_t local = 0;
+    for (int j = 0; j < 32; ++j) local += h[32 * lane + j];
+    uint32_t incl = local;  // keys in this lane's bins and all higher ones
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_down(incl, o);
+      if (lane + o < 64) incl += t;
+    }
+    uint32_t above = incl - local;
+    int digit = -1;
+    uint32_t nneed = 0;
+    if (above < need && need <= incl) {
+      for (int j = 31; j >= 0; --j) {
+        const uint32_t c = h[32 * lane + j];
+        if (above < need && need <= above + c) {
+          digit = 32 * lane + j;
+          nneed = need - above;
+        }
+        above += c;
+      }
+    }
+    const uint64_t owner = __ballot(digit >= 0);
+    const int src = __ffsll((unsigned long long)owner) - 1;
+    digit = __shfl(digit, src);
+    need = __shfl(nneed, src);
+    prefix |= (uint32_t)digit << shift;
+    wave_sync();
   }
+  float tau = unorder_f32(prefix);  // the smallest key with these 22 bits
+  if (tau != tau) tau = -INFINITY;   // a prefix below every finite score's key
   if (lane == 0) seed[q] = fmaxf(seed[q], tau);
 }
 
@@ -808,13 +849,44 @@ gv_status batched_run(std::vector<BatchEntry>& e, int k, int kappa, hipStream_t 
   }
   upload->assign(off_heads, 0);
 
+  // branches to streams: longest first onto the least loaded stream, by a rough
+  // time model of each search's branch (a launch latency per kernel, the S1
+  // FP64 product, the sample levels' reads and matrix-core work, the rerank's
+  // gathers)
+  auto assign = [&](const std::vector<double>& cost) {
+    std::vector<int> order(ne), to(ne);
+    for (int i = 0; i < ne; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<double> load(nside, 0.0);
+    for (int i : order) {
+      const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      to[i] = j;
+      load[j] += cost[i];
+    }
+    return to;
+  };
+  std::vector<double> c_pre(ne), c_suf(ne);
+  for (int i = 0; i < ne; ++i) {
+    const gv_index* ix = e[i].idx;
+    const double m = (double)e[i].m, C = ix->C, d = ix->d, D = ix->D, dp = plans[i].dp;
+    const double eb = ix->fmt == GV_FP32 ? 4.0 : (ix->fmt == GV_FP8_E4M3 ? 1.0 : 2.0);
+    double t = 15e-6 * (2.0 + 2.0 * (double)(plans[i].levels.size() - 1)) + 2.0 * m * C * d * D / 35e12;
+    for (size_t li = 0; li + 1 < plans[i].levels.size(); ++li) {
+      const double rows = (double)ix->n_rows / (double)plans[i].levels[li];
+      t += std::max(2.0 * m * rows * dp / 1e15, rows * dp * eb / 5e12);
+    }
+    c_pre[i] = t;
+    c_suf[i] = 30e-6 + m * kappa * D * 4.0 / 3e12 + m * 2e-8;
+  }
+  const std::vector<int> s_pre = assign(c_pre), s_suf = assign(c_suf);
+
   // ---- branches: projections and cascade levels before the full scans
   GV_HIP(hipEventRecord(fork, org));
   for (int j = 0; j < nside; ++j) GV_HIP(hipStreamWaitEvent(side[j], fork, 0));
   std::vector<ScoreArgs> last(ne);
   std::vector<Shape> last_sh(ne);
   for (int i = 0; i < ne; ++i) {
-    hipStream_t st = side[i % nside];
+    hipStream_t st = side[s_pre[i]];
     BatchEntry& b = e[i];
     uint8_t* ws = b.ws;
     float* t = (float*)(ws + b.plan.off_t);
@@ -828,10 +900,25 @@ gv_status batched_run(std::vector<BatchEntry>& e, int k, int kappa, hipStream_t 
     GV_HIP(hipEventRecord(join[j], side[j]));
     GV_HIP(hipStreamWaitEvent(org, join[j], 0));
   }
-  // ---- the full scans: one persistent queue launch per class
+  // ---- the full scans: one persistent queue launch per class, the classes on
+  // the side streams (a class's workgroups take the CUs another class's
+  // stragglers leave idle)
   hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, org, (int*)(qmem + off_heads), (int)cls.size());
   GV_HIP(hipGetLastError());
-  for (size_t c = 0; c < cls.size(); ++c) {
+  GV_HIP(hipEventRecord(fork, org));
+  for (int j = 0; j < nside; ++j) GV_HIP(hipStreamWaitEvent(side[j], fork, 0));
+  // largest classes first, each onto the least loaded stream
+  std::vector<double> c_cls(cls.size(), 0.0);
+  for (size_t c = 0; c < cls.size(); ++c)
+    for (int i : cls[c].members)
+      c_cls[c] += (double)e[i].m * (double)e[i].idx->n_rows * (double)plans[i].dp;
+  std::vector<int> corder(cls.size());
+  for (size_t c = 0; c < cls.size(); ++c) corder[c] = (int)c;
+  std::sort(corder.begin(), corder.end(), [&](int x, int y) { return c_cls[x] > c_cls[y]; });
+  std::vector<double> sload(nside, 0.0);
+  for (int c : corder) {
+    const int sj = (int)(std::min_element(sload.begin(), sload.end()) - sload.begin());
+    sload[sj] += c_cls[c];
     std::vector<int64_t> offs(cls[c].members.size() + 1, 0);
     for (size_t j = 0; j < cls[c].members.size(); ++j) {
       const int i = cls[c].members[j];
@@ -844,13 +931,17 @@ gv_status batched_run(std::vector<BatchEntry>& e, int k, int kappa, hipStream_t 
     const int grid = (int)std::min<int64_t>(offs.back(), (int64_t)n_cu * occ);
     GV_TRY(dispatch_fmt_queue(cls[c].fmt, cls[c].dp, rep, grid, (const ScoreArgs*)(qmem + off_args[c]),
                               (const int64_t*)(qmem + off_off[c]), (int)cls[c].members.size(),
-                              (int*)(qmem + off_heads) + c, org));
+                              (int*)(qmem + off_heads) + c, side[sj]));
+  }
+  for (int j = 0; j < nside; ++j) {
+    GV_HIP(hipEventRecord(join[j], side[j]));
+    GV_HIP(hipStreamWaitEvent(org, join[j], 0));
   }
   // ---- branches: final selects and reranks
   GV_HIP(hipEventRecord(fork, org));
   for (int j = 0; j < nside; ++j) GV_HIP(hipStreamWaitEvent(side[j], fork, 0));
   for (int i = 0; i < ne; ++i) {
-    hipStream_t st = side[i % nside];
+    hipStream_t st = side[s_suf[i]];
     BatchEntry& b = e[i];
     uint8_t* ws = b.ws;
     int32_t* cand = (int32_t*)(ws + b.plan.off_cand);

@@ -75,8 +75,10 @@ __device__ inline void wave_sync() {
 
 // kappa-th largest of the distinct keys load(0..cnt) (1 <= kappa <= cnt) by an
 // MSB-first radix select with 8-bit digits, for one wavefront; returns T with
-// exactly kappa keys >= T.  hist: 256 words of this wavefront's LDS.
-template <typename Load>
+// exactly kappa keys >= T.  hist: 256 words of this wavefront's LDS.  UNROLL
+// keys per lane are loaded before any is counted (loads from global memory
+// then overlap instead of each waiting for the last).
+template <int UNROLL = 1, typename Load>
 __device__ uint64_t wave_kth(Load load, int cnt, int kappa, uint32_t* hist) {
   const int lane = threadIdx.x & 63;
   uint64_t prefix = 0, mask = 0;
@@ -84,9 +86,13 @@ __device__ uint64_t wave_kth(Load load, int cnt, int kappa, uint32_t* hist) {
   for (int shift = 56; shift >= 0; shift -= 8) {
     for (int b = lane; b < 256; b += 64) hist[b] = 0;
     wave_sync();
-    for (int i = lane; i < cnt; i += 64) {
-      const uint64_t k = load(i);
-      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1u);
+    for (int i0 = lane; i0 < cnt; i0 += 64 * UNROLL) {
+      uint64_t k[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) k[u] = i0 + 64 * u < cnt ? load(i0 + 64 * u) : 0;
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u)
+        if (i0 + 64 * u < cnt && (k[u] & mask) == prefix) atomicAdd(&hist[(k[u] >> shift) & 255], 1u);
     }
     wave_sync();
     const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];

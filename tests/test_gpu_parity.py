@@ -197,6 +197,26 @@ def test_project_matches_oracle(gv, fmt, m):
         assert np.all(tb > 0)
 
 
+def test_project_large_tiles_matches_oracle(gv):
+    """S1 for a batch large enough for the 128 x 128 FP64 matrix-core tiles
+    (6600 queries x 8 clusters x 160 rows): q_c equals the oracle's fl32 of the
+    FP64 product wherever FP64 summation order cannot flip the rounding, and is
+    within one FP32 ulp everywhere."""
+    cfg, D, J, n, ml, d, C, _, kappa = CASES["d160-C8"]
+    m = 6600
+    _say(f"[project large tiles] m{m}")
+    X, QL, Q = problem(cfg, D, J, n, ml, m)
+    om = oracle_model(cfg, D, J, n, ml, d, C, 7)
+    model = gv.model_import(om.mu, om.A, om.B)
+    qc, t, qhat = gv.project(model, "fp16", dev(Q))
+    torch.cuda.synchronize()
+    ref_qc, ref_t, ref_qh = G.project_queries(om.A, Q, "fp16")
+    qc = qc.cpu().numpy().astype(np.float64)
+    assert np.all(qc[:, :, d:] == 0)
+    assert (qc[:, :, :d] == ref_qc).mean() > 0.9999
+    assert np.allclose(qc[:, :, :d], ref_qc, rtol=2 ** -23, atol=0)
+
+
 # ----------------------------------------------------------------------------- S2 + S3 (+ S4)
 
 REGIMES = [
