@@ -486,6 +486,22 @@ gv_status gv_rerank_stored(const gv_index* index, const float* qc, int64_t m, co
  */
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap);
 
+/*
+ * gv_search_optimism -- the seed of the full-database scan for the calling
+ * thread's following searches, when the cascade's last sample level filters
+ * (three or more levels).  Algorithm 1 needs the kappa best reduced scores;
+ * any score at or below the kappa-th best is a valid threshold.  By default
+ * (rank 0) the scan starts from the kappa_opt-th best score of that sample,
+ * kappa_opt = f kappa + 6 sqrt(f kappa) + 6 with f the sample's fraction of
+ * the rows, which keeps about kappa_opt / f keys instead of kappa / f; a query
+ * whose lists then hold fewer than kappa keys (its threshold was above its
+ * kappa-th best) is rescanned from the sample's kappa-th best, so results are
+ * exactly those of the plain scan.  rank > 0 takes the rank-th best sample
+ * score instead (small ranks force rescans: for tests); rank = -1 starts from
+ * the kappa-th best.  Results do not depend on it.  Errors: GV_EINVAL (rank < -1).
+ */
+gv_status gv_search_optimism(int32_t rank);
+
 /* One level of the S2/S3 launch plan (gv_scan_plan). */
 typedef struct {
   int64_t stride;            /* the level scans every stride-th 32-row tile (1: the whole database) */

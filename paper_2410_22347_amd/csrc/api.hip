@@ -21,6 +21,8 @@ void clear_error() { g_err.clear(); }
 int tuned_splits() { return g_splits; }
 int tuned_qpw() { return g_qpw; }
 int tuned_cap() { return g_cap; }
+static thread_local int g_optimism = 0;
+int tuned_optimism() { return g_optimism; }
 void set_tuning(int splits, int qpw, int cap) {
   g_splits = splits;
   g_qpw = qpw;
@@ -755,7 +757,7 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
     // every search keeps a workspace of its own: its lists live from its
     // cascade levels, through the shared full-scan launches, to its final select
     std::vector<uintptr_t> key{(uintptr_t)n_coll, (uintptr_t)k, (uintptr_t)kappa, (uintptr_t)stream, (uintptr_t)dev,
-                               (uintptr_t)tuned_splits(), (uintptr_t)tuned_qpw(), (uintptr_t)tuned_cap(),
+                               (uintptr_t)tuned_splits(), (uintptr_t)tuned_qpw(), (uintptr_t)tuned_cap(), (uintptr_t)tuned_optimism(),
                                (uintptr_t)tuning_table_version()};
     size_t ws_bytes = 0;
     for (int i = 0; i < n_coll; ++i) {
@@ -869,6 +871,16 @@ gv_status gv_scan_plan(int64_t n, int64_t n_pad, int32_t C, gv_format fmt, int32
     if (n_levels) *n_levels = nl;
     return GV_OK;
   });
+}
+
+gv_status gv_search_optimism(int32_t rank) {
+  clear_error();
+  if (rank < -1) {
+    set_error("gv_search_optimism: rank must be -1, 0 or positive");
+    return GV_EINVAL;
+  }
+  g_optimism = rank;
+  return GV_OK;
 }
 
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap) {

@@ -334,6 +334,7 @@ void set_eig_step_limit(long max_steps);
 int tuned_splits();
 int tuned_qpw();
 int tuned_cap();
+int tuned_optimism();  // the optimistic seed's rank override (gv_search_optimism)
 // Launch overrides of S2/S3 (0: automatic).  The calling thread's overrides
 // (gv_search_tuning) come first; else the autotuner's table entry for the
 // search's shape class (format, padded length, batch class, size class).

@@ -107,6 +107,27 @@ __global__ void k_zero_ints(int* __restrict__ p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
+// After an optimistic full scan (see run_scan): a query whose lists hold fewer
+// than kappa keys may have missed some of its kappa best (its seed lay above its
+// kappa-th best score), so its lists are emptied and it is rescanned from the
+// exact seed; every other query gets +inf, which the repair pass leaves alone.
+// One wavefront per query.
+__global__ __launch_bounds__(256) void k_repair_prep(int32_t* __restrict__ cnt, int R, int64_t m, int kappa,
+                                                     const float* __restrict__ seed,
+                                                     const float* __restrict__ seed_opt, float* __restrict__ rescan) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= m) return;
+  int32_t* c = cnt + q * R;
+  long long total = 0;
+  for (int r = lane; r < R; r += 64) total += c[r];
+  for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
+  const bool redo = total < kappa && seed_opt[q] > seed[q];
+  if (redo)
+    for (int r = lane; r < R; r += 64) c[r] = 0;
+  if (lane == 0) rescan[q] = redo ? seed[q] : INFINITY;
+}
+
 // seed[q] = -inf
 __global__ void k_seed_init(int64_t m, float* __restrict__ seed) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -225,11 +246,14 @@ __host__ __device__ inline int pow2_at_least(int v) {
   return p;
 }
 
+// seed_opt (sample levels, may be null): also the kappa_opt-th best score, an
+// optimistic seed for the next level (see run_scan).
 template <bool FINAL>
 __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf, const int32_t* __restrict__ cnt,
                                                 int R, int cap, int kappa, const int32_t* __restrict__ ids,
                                                 float* __restrict__ seed, int32_t* __restrict__ out_ids,
-                                                float* __restrict__ out_scores) {
+                                                float* __restrict__ out_scores, float* __restrict__ seed_opt,
+                                                int kappa_opt) {
   __shared__ uint64_t keys[kSelWin];
   __shared__ int32_t pre[kMaxLists + 1];
   __shared__ uint64_t stage[kMaxKappa];
@@ -323,16 +347,23 @@ __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf
   }
 
   if (!FINAL) {
-    if (kept < kappa) return;  // fewer than kappa candidates: no bound
+    if (kept < kappa) {  // fewer than kappa candidates: no bound
+      if (seed_opt && tid == 0) seed_opt[q] = seed[q];
+      return;
+    }
     // the kappa-th best is the smallest kept key
     uint64_t mn = ~0ull;
     for (int i = tid; i < kept; i += 256) mn = std::min(mn, keys[i]);
     for (int o = 32; o > 0; o >>= 1) mn = std::min(mn, (uint64_t)__shfl_xor(mn, o));
     if (lane == 0) stage[wave] = mn;
     __syncthreads();
+    float opt = -INFINITY;
+    if (seed_opt) opt = key_score(block_kth(keys, kept, kappa_opt, sel));  // every thread takes part
     if (tid == 0) {
       const uint64_t m4 = std::min(std::min(stage[0], stage[1]), std::min(stage[2], stage[3]));
-      seed[q] = fmaxf(seed[q], key_score(m4));
+      const float sd = fmaxf(seed[q], key_score(m4));
+      seed[q] = sd;
+      if (seed_opt) seed_opt[q] = fmaxf(sd, opt);
     }
     return;
   }
@@ -457,7 +488,12 @@ struct ScanPlan {
   int64_t ns = 0;
   int cap = kCap;
   int dp = 0;  // padded length of the scanned leading part of each row
-  size_t off_buf = 0, off_cnt = 0, off_seed = 0, off_dense = 0, bytes = 0;
+  // the full scan starts from an optimistic seed, the kappa_opt-th best score
+  // of the last sample level, and a repair pass rescans the rare queries for
+  // which it kept fewer than kappa keys (see run_scan)
+  bool optimistic = false;
+  int kappa_opt = 0;
+  size_t off_buf = 0, off_cnt = 0, off_seed = 0, off_dense = 0, off_seed_opt = 0, off_rescan = 0, bytes = 0;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -533,6 +569,25 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
     p->limits.push_back(lm);
   }
   p->ns = p->has_dense ? ((ntiles + p->levels[0] - 1) / p->levels[0]) * kRows : 0;
+  // Optimistic seed of the full scan, when the level before it filters.  If a
+  // sample holds each row with probability f, the number of its rows among a
+  // query's kappa - 1 best is about Binomial(kappa, f); the kappa_opt-th best
+  // sample score exceeds the query's kappa-th best only if that count reaches
+  // kappa_opt = f kappa + 6 sqrt(f kappa) + 6 (six standard deviations, plus
+  // room for small kappa).  About kappa_opt / f keys then survive instead of
+  // kappa / f, and the repair pass keeps the result exact when the bound fails.
+  p->optimistic = false;
+  p->kappa_opt = 0;
+  const size_t nl = p->levels.size();
+  const int ov = tuned_optimism();
+  if (nl >= 3 && ov >= 0) {
+    const double mu = (double)kappa * (double)p->levels[nl - 1] / (double)p->levels[nl - 2];
+    const int ko = ov > 0 ? ov : (int)std::ceil(mu + 6.0 * std::sqrt(mu) + 6.0);
+    if (ko < kappa) {
+      p->optimistic = true;
+      p->kappa_opt = ko;
+    }
+  }
   const uint64_t keys = (uint64_t)m * p->Rmax * p->cap;
   if (keys >= (1ull << 32)) {  // list slots are staged as 32-bit indices
     set_error("search batch too large for the candidate lists (reduce m)");
@@ -544,6 +599,8 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
   p->off_cnt = o;   o = align256(o + sizeof(int32_t) * m * p->Rmax);
   p->off_seed = o;  o = align256(o + (p->has_dense ? sizeof(float) * m : 0));
   p->off_dense = o; o = align256(o + (p->has_dense ? sizeof(float) * m * p->ns : 0));
+  p->off_seed_opt = o; o = align256(o + (p->optimistic ? sizeof(float) * m : 0));
+  p->off_rescan = o;   o = align256(o + (p->optimistic ? sizeof(float) * m : 0));
   p->bytes = o;
   return GV_OK;
 }
@@ -573,6 +630,8 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
   int32_t* cnt = (int32_t*)(ws + p.off_cnt);
   float* seed = p.has_dense ? (float*)(ws + p.off_seed) : nullptr;
   float* dense = p.has_dense ? (float*)(ws + p.off_dense) : nullptr;
+  float* seed_opt = p.optimistic ? (float*)(ws + p.off_seed_opt) : nullptr;
+  float* rescan = p.optimistic ? (float*)(ws + p.off_rescan) : nullptr;
   const int fmt = idx->fmt;
 
   ScoreArgs args{};
@@ -605,6 +664,19 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     if (lazy) return dense ? dispatch_scan_lazy<kDense>(sh_cur, args, st) : dispatch_scan_lazy<kFilter>(sh_cur, args, st);
     return dense ? dispatch_fmt<kDense>(fmt, p.dp, sh_cur, args, st) : dispatch_fmt<kFilter>(fmt, p.dp, sh_cur, args, st);
   };
+  // after the optimistic full scan (args and sh_cur set for it): queries that
+  // kept fewer than kappa keys are rescanned from the exact seed
+  auto repair = [&]() -> gv_status {
+    hipLaunchKernelGGL(k_repair_prep, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, cnt, sh_cur.R, m, kappa, seed,
+                       seed_opt, rescan);
+    const float* s0 = args.seed;
+    args.seed = rescan;
+    args.repair = 1;
+    const gv_status r = dispatch(false);
+    args.seed = s0;
+    args.repair = 0;
+    return r;
+  };
 
   gv_status s = GV_OK;
   if (p.has_dense && part != Part::Suffix)
@@ -613,7 +685,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     const Shape& sh = p.shapes[li];
     sh_cur = sh;
     const bool last = li + 1 == p.levels.size();
-    args.seed = li == 0 ? nullptr : seed;
+    args.seed = li == 0 ? nullptr : (last && p.optimistic ? seed_opt : seed);
     args.R = sh.R;
     args.nqb = (int)sh.nqb;
     args.stride = (int)p.levels[li];
@@ -630,8 +702,10 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
       break;
     }
     if (part == Part::Suffix) {
+      if (p.optimistic) s = repair();
+      if (s != GV_OK) break;
       hipLaunchKernelGGL(k_select<true>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, p.cap, kappa, idx->ids,
-                         seed, cand_ids, cand_scores);
+                         seed, cand_ids, cand_scores, (float*)nullptr, 0);
       break;
     }
     if (p.has_dense && li == 0) {
@@ -650,13 +724,18 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     if (last) profile_mark(st, 0, false);
     if (s != GV_OK) break;
     if (last) {
+      if (p.optimistic) s = repair();
+      if (s != GV_OK) break;
       profile_mark(st, 1, true);
       hipLaunchKernelGGL(k_select<true>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, p.cap, kappa, idx->ids,
-                         seed, cand_ids, cand_scores);
+                         seed, cand_ids, cand_scores, (float*)nullptr, 0);
       profile_mark(st, 1, false);
     } else {
+      // the level before the full scan also yields the optimistic seed
+      const bool feeds_full = li + 2 == p.levels.size() && p.optimistic;
       hipLaunchKernelGGL(k_select<false>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, p.cap, kappa,
-                         idx->ids, seed, (int32_t*)nullptr, (float*)nullptr);
+                         idx->ids, seed, (int32_t*)nullptr, (float*)nullptr, feeds_full ? seed_opt : (float*)nullptr,
+                         p.kappa_opt);
     }
   }
   GV_TRY(s);
@@ -946,8 +1025,8 @@ gv_status batched_run(std::vector<BatchEntry>& e, int k, int kappa, hipStream_t 
     uint8_t* ws = b.ws;
     int32_t* cand = (int32_t*)(ws + b.plan.off_cand);
     float* csc = (float*)(ws + b.plan.off_csc);
-    GV_TRY(run_scan(b.idx, plans[i], ws + b.plan.off_scan, nullptr, nullptr, b.m, kappa, cand, csc, st, nullptr,
-                    Part::Suffix));
+    GV_TRY(run_scan(b.idx, plans[i], ws + b.plan.off_scan, ws + b.plan.off_qhat, (float*)(ws + b.plan.off_t), b.m,
+                    kappa, cand, csc, st, nullptr, Part::Suffix));
     if (b.plan.stored) {
       float* qc = (float*)(ws + b.plan.off_qc);
       GV_TRY(rerank_stored_impl(b.idx, qc, b.m, cand, kappa, k, b.out_ids, b.out_scores, st));

@@ -66,6 +66,10 @@ struct ScoreArgs {
   const float* lazy_Q;   // m x lazy_D FP32 queries
   int lazy_d, lazy_D;    // the model's reduced and full dimension
   int lazy_ds;           // leading coordinates in the view (d_search)
+  // 1: a repair pass after an optimistic full scan -- only queries with a finite
+  // seed are rescanned (their lists were emptied); the others' lists and
+  // lengths are left as they are, and a workgroup without such a query leaves
+  int repair;
 };
 
 __device__ inline void wave_sync() {
@@ -389,6 +393,20 @@ __device__ __forceinline__ void scan_body(const ScoreArgs& a, const int b_item) 
       qb = qg * 4 + wave;
       r = rr;
     }
+  }
+  if (a.repair) {  // the same branch for the whole workgroup (a kernel argument)
+    __shared__ int s_need;
+    if (threadIdx.x == 0) s_need = 0;
+    __syncthreads();
+    bool need = false;
+    if (qb < a.nqb)
+      for (int i = lane; i < QW; i += 64) {
+        const int64_t q = (int64_t)qb * QW + i;
+        need |= q < a.m && a.seed[q] < INFINITY;
+      }
+    if (__ballot(need) != 0 && lane == 0) atomicOr(&s_need, 1);
+    __syncthreads();
+    if (s_need == 0) return;
   }
   // padding work item of the last query group (with a shared tile ring it still
   // loads its share of the tiles and meets every barrier; its queries are void)
@@ -799,7 +817,7 @@ __device__ __forceinline__ void scan_body(const ScoreArgs& a, const int b_item) 
       Unroll<0, NB>::run([&](auto nbc) __attribute__((always_inline)) {
         constexpr int nb = decltype(nbc)::value;
         const int64_t q = q0 + nb * 32 + col;
-        if (q < a.m) a.cnt_out[q * a.R + r] = cnt[nb];
+        if (q < a.m && (!a.repair || a.seed[q] < INFINITY)) a.cnt_out[q * a.R + r] = cnt[nb];
       });
     }
   }
@@ -809,6 +827,13 @@ template <int FMT, int KS, int NB, bool SHARED, int MODE, int P, bool DEFER, int
           bool LAZY = false>
 __global__ __launch_bounds__(256, OCC) void k_scan(ScoreArgs a) {
   scan_body<FMT, KS, NB, SHARED, MODE, P, DEFER, OCC, FULL, WGT, PL, LAZY>(a, blockIdx.x);
+}
+
+// The repair pass of an optimistic full scan (a.repair = 1): the same scan,
+// under its own name so that kernel traces keep the two launches apart.
+template <int FMT, int KS, int NB, bool SHARED, int P, bool DEFER, int OCC, bool WGT, int PL, bool LAZY = false>
+__global__ __launch_bounds__(256, OCC) void k_scan_repair(ScoreArgs a) {
+  scan_body<FMT, KS, NB, SHARED, kFilter, P, DEFER, OCC, true, WGT, PL, LAZY>(a, blockIdx.x);
 }
 
 // Persistent form: workgroups pull pieces (c, b) -- search c, piece b of its
@@ -897,7 +922,10 @@ struct KernelCfg {
 template <int FMT, int KS, int NB, bool SHARED, int MODE>
 void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   using K = KernelCfg<FMT, KS, NB, SHARED>;
-  if (MODE == kFilter && args.stride == 1)
+  if (MODE == kFilter && args.stride == 1 && args.repair)
+    hipLaunchKernelGGL((k_scan_repair<FMT, KS, NB, SHARED, K::P, K::DEF, K::OC, K::W, K::PL>), dim3(sh.grid),
+                       dim3(256), 0, st, args);
+  else if (MODE == kFilter && args.stride == 1)
     hipLaunchKernelGGL((k_scan<FMT, KS, NB, SHARED, MODE, K::P, K::DEF, K::OC, true, K::W, K::PL>), dim3(sh.grid),
                        dim3(256), 0, st, args);
   else
@@ -910,7 +938,10 @@ void launch_one(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
 template <int MODE>
 void launch_lazy(const Shape& sh, const ScoreArgs& args, hipStream_t st) {
   using K = KernelCfg<GV_FP16, 10, 1, true>;
-  if (MODE == kFilter && args.stride == 1)
+  if (MODE == kFilter && args.stride == 1 && args.repair)
+    hipLaunchKernelGGL((k_scan_repair<GV_FP16, 10, 1, true, K::P, K::DEF, K::OC, K::W, K::PL, true>), dim3(sh.grid),
+                       dim3(256), 0, st, args);
+  else if (MODE == kFilter && args.stride == 1)
     hipLaunchKernelGGL((k_scan<GV_FP16, 10, 1, true, MODE, K::P, K::DEF, K::OC, true, K::W, K::PL, true>),
                        dim3(sh.grid), dim3(256), 0, st, args);
   else

@@ -177,3 +177,25 @@ def test_autotune_keeps_results_and_feeds_the_table(gv, collections):
     assert torch.equal(out[4][0], ref[0]) and torch.equal(out[4][1], ref[1])
     gv.batch_release()
     gv.tuning_table_clear()
+
+
+def test_batched_optimistic_seed_repair(gv, collections):
+    """kappa = 10 gives the collections of 10^4 rows and more a three-level
+    cascade; with the optimistic seed forced to the best sample score, almost
+    every query is repaired -- in the persistent batched executor as in the single
+    searches -- and the results equal the automatic ones."""
+    k, kappa = 10, 10
+    models = [md for _, md, _, _ in collections]
+    indexes = [ix for _, _, ix, _ in collections]
+    Qs = [Q for _, _, _, Q in collections]
+    ref = _eager(gv, collections, k, kappa)
+    try:
+        gv.search_optimism(1)
+        forced = _eager(gv, collections, k, kappa)
+        out = gv.search_batched(models, indexes, Qs, k, kappa)
+        torch.cuda.synchronize()
+        _same(forced, ref)
+        _same(out, ref)
+    finally:
+        gv.search_optimism(0)
+        gv.batch_release()

@@ -111,6 +111,8 @@ def test_host_argument_errors():
     assert lib.gv_search_tuning(0, 0, 50) == -1
     assert lib.gv_search_tuning(5000, 0, 0) == -1
     assert lib.gv_search_tuning(0, 0, 0) == 0
+    assert lib.gv_search_optimism(-2) == -1
+    assert lib.gv_search_optimism(3) == 0 and lib.gv_search_optimism(-1) == 0 and lib.gv_search_optimism(0) == 0
     lib.gv_model_destroy(None)
     lib.gv_index_destroy(None)
 
