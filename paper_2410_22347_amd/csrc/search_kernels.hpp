@@ -147,15 +147,17 @@ constexpr int wave_smem_bytes(int qw, int capl) { return (qw * 4 + 256 * 4 + 4 +
 constexpr int lds_budget(int occ) { return 160 * 1024 / occ - 256; }  // some room for the queue kernel's own words
 template <int FMT, int KS>
 constexpr int ring_tile_bytes() { return KS * 64 * MfmaOp<FMT>::EPL * MfmaOp<FMT>::EB; }
-// tiles of a ring shared by two workgroups per CU: four where they fit beside a
-// staging of half a list, else three (the fewest the pipeline needs)
+// tiles of a ring shared by two workgroups per CU: the deepest ring, up to five
+// tiles (the copies of three tiles in flight while one is scored), that fits
+// beside a 768-key staging; three is the fewest the pipeline needs
 template <int FMT, int KS, int NB>
 constexpr int ring_tiles_two_per_cu() {
-  return 4 * wave_smem_bytes(32 * NB, kCap / 2) + 4 * ring_tile_bytes<FMT, KS>() <= lds_budget(2) ? 4 : 3;
+  for (int pl = 5; pl > 3; --pl)
+    if (4 * wave_smem_bytes(32 * NB, 768) + pl * ring_tile_bytes<FMT, KS>() <= lds_budget(2)) return pl;
+  return 3;
 }
 // keys a compaction can stage: the whole list with one workgroup per CU and no
-// ring; else half a list, or 768 keys where a ring of the longest tiles leaves
-// no room for half a list
+// ring; else half a list where it fits beside the ring, or 768 keys
 template <int FMT, int KS, int NB, int OCC, bool WGT, int PL>
 constexpr int staging_keys() {
   if (!(OCC >= 2 || WGT)) return kCap;
@@ -903,8 +905,8 @@ struct RingCfg {
 // wavefront on the LDS ring, two workgroups share a CU (two wavefronts per SIMD,
 // 256 registers each): one wavefront's filter, barrier and LDS waits overlap the
 // other's matrix-core chain.  Two such workgroups must fit the LDS: the ring is
-// four tiles deep and the compaction staging 1024 keys up to 10 KiB tiles; 12
-// KiB tiles take a ring of three; 16 KiB tiles a ring of three and 768 keys.
+// five tiles deep up to 10 KiB tiles (with a 768-key compaction staging at 10
+// KiB, 1024 below), four at 12 KiB, three at 16 KiB (768 keys at both).
 template <int FMT, int KS, int NB, bool SHARED>
 struct KernelCfg {
   using Cfg = ScanCfg<FMT, KS, NB>;
