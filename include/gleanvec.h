@@ -487,18 +487,21 @@ gv_status gv_rerank_stored(const gv_index* index, const float* qc, int64_t m, co
 gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap);
 
 /*
- * gv_search_optimism -- the seed of the full-database scan for the calling
- * thread's following searches, when the cascade's last sample level filters
- * (three or more levels).  Algorithm 1 needs the kappa best reduced scores;
- * any score at or below the kappa-th best is a valid threshold.  By default
- * (rank 0) the scan starts from the kappa_opt-th best score of that sample,
- * kappa_opt = f kappa + 6 sqrt(f kappa) + 6 with f the sample's fraction of
- * the rows, which keeps about kappa_opt / f keys instead of kappa / f; a query
- * whose lists then hold fewer than kappa keys (its threshold was above its
- * kappa-th best) is rescanned from the sample's kappa-th best, so results are
- * exactly those of the plain scan.  rank > 0 takes the rank-th best sample
- * score instead (small ranks force rescans: for tests); rank = -1 starts from
- * the kappa-th best.  Results do not depend on it.  Errors: GV_EINVAL (rank < -1).
+ * gv_search_optimism -- the seeds of the cascade's levels after the first
+ * filtering one, for the calling thread's following searches, when the level
+ * before the full scan filters (three or more levels).  Algorithm 1 needs the
+ * kappa best reduced scores; any score at or below a query's kappa-th best is a
+ * valid threshold.  By default (rank 0) a level starts from the kappa_opt-th
+ * best score of the level before, kappa_opt = f kappa + 6 sqrt(f kappa) + 6
+ * with f the fraction of the level's rows the level before samples, which
+ * keeps about kappa_opt / f keys instead of kappa / f.  A query whose
+ * full-scan lists then hold fewer than kappa keys (its threshold was above its
+ * kappa-th best) is rescanned from the exact seed, so results are exactly
+ * those of the plain scan; a sample level that keeps fewer than kappa keys
+ * leaves the exact seed of the level before in place.  rank > 0 takes the
+ * rank-th best score instead (small ranks force rescans: for tests); rank = -1
+ * starts every level from the exact kappa-th best.  Results do not depend on
+ * it.  Errors: GV_EINVAL (rank < -1).
  */
 gv_status gv_search_optimism(int32_t rank);
 

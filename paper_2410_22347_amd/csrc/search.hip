@@ -569,13 +569,16 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
     p->limits.push_back(lm);
   }
   p->ns = p->has_dense ? ((ntiles + p->levels[0] - 1) / p->levels[0]) * kRows : 0;
-  // Optimistic seed of the full scan, when the level before it filters.  If a
-  // sample holds each row with probability f, the number of its rows among a
-  // query's kappa - 1 best is about Binomial(kappa, f); the kappa_opt-th best
-  // sample score exceeds the query's kappa-th best only if that count reaches
-  // kappa_opt = f kappa + 6 sqrt(f kappa) + 6 (six standard deviations, plus
-  // room for small kappa).  About kappa_opt / f keys then survive instead of
-  // kappa / f, and the repair pass keeps the result exact when the bound fails.
+  // Optimistic seeds, when the level before the full scan filters: every level
+  // after the first filtering one starts from the kappa_opt-th best score of
+  // the level before.  If a sample holds each row of the next level with
+  // probability f, the number of its rows among a query's kappa - 1 best there
+  // is about Binomial(kappa, f); the kappa_opt-th best sample score exceeds the
+  // query's kappa-th best only if that count reaches kappa_opt = f kappa +
+  // 6 sqrt(f kappa) + 6 (six standard deviations, plus room for small kappa).
+  // About kappa_opt / f keys then survive instead of kappa / f.  The full scan's
+  // repair pass keeps its result exact; a sample level that keeps fewer than
+  // kappa keys leaves the exact seed of the level before in place.
   p->optimistic = false;
   p->kappa_opt = 0;
   const size_t nl = p->levels.size();
@@ -685,7 +688,10 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     const Shape& sh = p.shapes[li];
     sh_cur = sh;
     const bool last = li + 1 == p.levels.size();
-    args.seed = li == 0 ? nullptr : (last && p.optimistic ? seed_opt : seed);
+    // levels after the first filtering one start from the optimistic seed of
+    // the level before (the full scan repairs what it misses; a sample level
+    // that keeps fewer than kappa keys leaves the exact seed as it was)
+    args.seed = li == 0 ? nullptr : (p.optimistic && li >= 2 ? seed_opt : seed);
     args.R = sh.R;
     args.nqb = (int)sh.nqb;
     args.stride = (int)p.levels[li];
@@ -731,10 +737,9 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
                          seed, cand_ids, cand_scores, (float*)nullptr, 0);
       profile_mark(st, 1, false);
     } else {
-      // the level before the full scan also yields the optimistic seed
-      const bool feeds_full = li + 2 == p.levels.size() && p.optimistic;
+      // a sample level also yields the optimistic seed of the next level
       hipLaunchKernelGGL(k_select<false>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, p.cap, kappa,
-                         idx->ids, seed, (int32_t*)nullptr, (float*)nullptr, feeds_full ? seed_opt : (float*)nullptr,
+                         idx->ids, seed, (int32_t*)nullptr, (float*)nullptr, p.optimistic ? seed_opt : (float*)nullptr,
                          p.kappa_opt);
     }
   }
