@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ 
 // FINAL: the kappa best, sorted, as (ids, scores) (-1 / NaN past the end when
 // fewer exist).  Otherwise: seed[q] = max(seed[q], kappa-th best score).
 constexpr int kSelWin = 4096;
+constexpr uint64_t kListBudget = 2ull << 30;  // bytes of candidate lists an automatic plan may take
 constexpr int kMaxLists = 4096;
 static_assert(kMaxKappa <= kSelWin / 2, "a select window holds the kappa kept keys and as many new ones");
 
@@ -381,7 +382,11 @@ __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf
 
 // whole_lists: one query block per workgroup (no tile ring), whose wavefronts
 // stage a whole list in a compaction -- for kappa beyond a ring shape's staging
-Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C, const Tuning& tu, bool whole_lists = false) {
+// wave_mul: workgroups per query group of a many-query scan, as a multiple of
+// the base count (shorter row ranges keep the workgroups that share a range in
+// step, so their tiles stay in L2; each range costs one list per query)
+Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C, const Tuning& tu, bool whole_lists = false,
+                   int wave_mul = 1) {
   Shape sh;
   const int qpw_override = tu.qpw;
   if (whole_lists) {
@@ -404,9 +409,9 @@ Shape choose_shape(int fmt, int dp, int64_t m, int64_t rows, int C, const Tuning
   sh.nqb = (m + 32 * sh.nb - 1) / (32 * sh.nb);
   const int64_t ntiles = rows / kRows + C;
   // about 1024 wavefronts (one per SIMD) when the query blocks share a workgroup's
-  // rows, 2048 (two rounds of workgroups, which evens out ranges that hold many
-  // survivors) otherwise; at least 4 tiles per range
-  const int64_t waves = sh.shared ? 1024 : 2048;
+  // rows, 2048 times wave_mul otherwise (several rounds of workgroups, which
+  // even out ranges that hold many survivors); at least 4 tiles per range
+  const int64_t waves = sh.shared ? 1024 : 2048LL * wave_mul;
   int64_t R = tu.splits > 0 ? tu.splits : std::max<int64_t>(1, waves / sh.nqb);
   R = std::min<int64_t>(R, std::max<int64_t>(1, ntiles / 4));
   R = std::min<int64_t>(R, kMaxLists);
@@ -531,43 +536,57 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
     return GV_EUNSUPPORTED;
   }
   const Tuning tu = effective_tuning(fmt, p->dp, m, n);
-  p->cap = tu.cap > 0 ? tu.cap : kCap;
-  if (p->cap <= kappa || p->cap > kCap) {
-    set_error("candidate list capacity must lie in (kappa, 2048]");
-    return GV_EINVAL;
-  }
   p->levels = cascade(n, kappa);
   p->has_dense = p->levels.size() > 1;
   const int64_t ntiles = n_pad / kRows;
-  p->shapes.clear();
-  p->limits.clear();
-  p->Rmax = 1;
-  for (size_t li = 0; li < p->levels.size(); ++li) {
-    const int64_t s = p->levels[li];
-    const int64_t rows = (ntiles + s - 1) / s * kRows;
-    Shape sh = choose_shape(fmt, p->dp, m, rows, C, tu);
-    ScanLimits lm = scan_limits(fmt, p->dp, sh);
-    const bool dense = p->has_dense && li == 0;  // the dense scan writes no lists
-    if (!dense) {
-      // a list is compacted once it holds more than lim keys and may then grow
-      // by 32 keys per tile for U + 1 tiles before the next check: the staging
-      // (CAPL) and the list (cap) must hold that, and a compaction to the kappa
-      // best must leave room (lim > kappa)
-      auto limit = [&](const ScanLimits& l) { return std::min(p->cap, l.CAPL) - kRows * (l.U + 1); };
-      if (limit(lm) <= kappa && !sh.shared) {  // a shape that stages whole lists
-        sh = choose_shape(fmt, p->dp, m, rows, C, tu, true);
-        lm = scan_limits(fmt, p->dp, sh);
+  // the shapes of every level for a list capacity and a workgroup multiple;
+  // GV_OK when every filtering level leaves a list room above kappa
+  auto build = [&](int cap, int wave_mul) -> gv_status {
+    p->cap = cap;
+    p->shapes.clear();
+    p->limits.clear();
+    p->Rmax = 1;
+    for (size_t li = 0; li < p->levels.size(); ++li) {
+      const int64_t s = p->levels[li];
+      const int64_t rows = (ntiles + s - 1) / s * kRows;
+      Shape sh = choose_shape(fmt, p->dp, m, rows, C, tu, false, wave_mul);
+      ScanLimits lm = scan_limits(fmt, p->dp, sh);
+      const bool dense = p->has_dense && li == 0;  // the dense scan writes no lists
+      if (!dense) {
+        // a list is compacted once it holds more than lim keys and may then grow
+        // by 32 keys per tile for U + 1 tiles before the next check: the staging
+        // (CAPL) and the list (cap) must hold that, and a compaction to the kappa
+        // best must leave room (lim > kappa)
+        auto limit = [&](const ScanLimits& l) { return std::min(p->cap, l.CAPL) - kRows * (l.U + 1); };
+        if (limit(lm) <= kappa && !sh.shared) {  // a shape that stages whole lists
+          sh = choose_shape(fmt, p->dp, m, rows, C, tu, true, wave_mul);
+          lm = scan_limits(fmt, p->dp, sh);
+        }
+        p->Rmax = std::max(p->Rmax, sh.R);
+        if (limit(lm) <= kappa) {
+          set_error("kappa too large for the candidate lists of this launch shape (reduce kappa or raise the list cap)");
+          return GV_EUNSUPPORTED;
+        }
       }
-      p->Rmax = std::max(p->Rmax, sh.R);
-      const int lim = limit(lm);
-      if (lim <= kappa) {
-        set_error("kappa too large for the candidate lists of this launch shape (reduce kappa or raise the list cap)");
-        return GV_EUNSUPPORTED;
-      }
+      p->shapes.push_back(sh);
+      p->limits.push_back(lm);
     }
-    p->shapes.push_back(sh);
-    p->limits.push_back(lm);
+    return GV_OK;
+  };
+  if (tu.cap > 0 && (tu.cap <= kappa || tu.cap > kCap)) {
+    set_error("candidate list capacity must lie in (kappa, 2048]");
+    return GV_EINVAL;
   }
+  bool chosen = false;
+  if (tu.cap == 0 && tu.splits == 0) {
+    // automatic: the most workgroups (up to eight times the base count) with
+    // the smallest list capacity (at least 512) whose lists fit in kListBudget
+    for (int mul = 8; mul >= 1 && !chosen; mul /= 2)
+      for (int cap = 512; cap <= kCap && !chosen; cap *= 2)
+        chosen = build(cap, mul) == GV_OK && (uint64_t)m * p->Rmax * cap * sizeof(uint64_t) <= kListBudget;
+    clear_error();
+  }
+  if (!chosen) GV_TRY(build(tu.cap > 0 ? tu.cap : kCap, 1));
   p->ns = p->has_dense ? ((ntiles + p->levels[0] - 1) / p->levels[0]) * kRows : 0;
   // Optimistic seeds, when the level before the full scan filters: every level
   // after the first filtering one starts from the kappa_opt-th best score of
