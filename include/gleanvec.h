@@ -505,6 +505,19 @@ gv_status gv_search_tuning(int32_t splits, int32_t qpw, int32_t cap);
  */
 gv_status gv_search_optimism(int32_t rank);
 
+/*
+ * gv_debug_fail_alloc -- for tests of the out-of-memory paths: after `after`
+ * more device allocations by the library (any thread), the next one fails as if
+ * the device were out of memory; the call that made it returns GV_ENOMEM and
+ * releases what it had allocated.  -1 turns it off.  Allocations of the
+ * caller's framework (e.g. torch tensors) are not counted.
+ * Errors: GV_EINVAL (after < -1).
+ */
+gv_status gv_debug_fail_alloc(int32_t after);
+/* the count gv_debug_fail_alloc set, less the allocations made since; -1 once
+ * the failure has happened (or when off) */
+int32_t gv_debug_allocs_pending(void);
+
 /* One level of the S2/S3 launch plan (gv_scan_plan). */
 typedef struct {
   int64_t stride;            /* the level scans every stride-th 32-row tile (1: the whole database) */

@@ -27,7 +27,8 @@ EXPORTED = [
     "gv_status_string", "gv_last_error", "gv_fit", "gv_model_import", "gv_model_shape",
     "gv_model_export", "gv_model_stats", "gv_model_destroy", "gv_encode", "gv_index_shape",
     "gv_index_export", "gv_index_destroy", "gv_search", "gv_project", "gv_score_topk",
-    "gv_rerank", "gv_search_tuning", "gv_search_optimism", "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
+    "gv_rerank", "gv_search_tuning", "gv_search_optimism", "gv_debug_fail_alloc", "gv_debug_allocs_pending",
+    "gv_host_eigh", "gv_profile_enable", "gv_profile_read",
     "gv_padded_dim", "gv_tags", "gv_moments", "gv_loss_grad", "gv_search_batched", "gv_batch_release",
     "gv_search_flex", "gv_project_flex", "gv_score_topk_flex", "gv_rerank_stored", "gv_augment",
     "gv_moments_update", "gv_fit_from_stats", "gv_batch_counts", "gv_eig_step_limit",
@@ -89,6 +90,8 @@ _sig("gv_score_topk", [_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp])
 _sig("gv_rerank", [_vp, _vp, _i64, _vp, _i32, _i32, _vp, _vp, _vp])
 _sig("gv_search_tuning", [_i32, _i32, _i32])
 _sig("gv_search_optimism", [_i32])
+_sig("gv_debug_fail_alloc", [_i32])
+_sig("gv_debug_allocs_pending", [], _i32)
 _sig("gv_augment", [_vp, _i64, _i32, _i32, _vp, _vp])
 _sig("gv_moments_update", [_vp, _i64, _i32, _vp, _i32, _i32, _vp, _vp])
 _sig("gv_fit_from_stats", [_vp, _vp, ctypes.c_double, _vp, _vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)])
@@ -449,6 +452,16 @@ def rerank(index: Index, Q, cand_ids, k: int):
 
 def search_tuning(splits: int = 0, qpw: int = 0, cap: int = 0):
     _check(_lib.gv_search_tuning(splits, qpw, cap), "gv_search_tuning")
+
+
+def debug_fail_alloc(after: int = -1):
+    """gv_debug_fail_alloc: the library's (after + 1)-th device allocation from now
+    fails as out of memory (-1: off).  For tests."""
+    _check(_lib.gv_debug_fail_alloc(after), "gv_debug_fail_alloc")
+
+
+def debug_allocs_pending() -> int:
+    return int(_lib.gv_debug_allocs_pending())
 
 
 def search_optimism(rank: int = 0):

@@ -23,6 +23,17 @@ int tuned_qpw() { return g_qpw; }
 int tuned_cap() { return g_cap; }
 static thread_local int g_optimism = 0;
 int tuned_optimism() { return g_optimism; }
+
+// forced allocation failure (gv_debug_fail_alloc): the allocation that finds
+// the count at 0 fails; -1 is off
+static std::atomic<long> g_fail_alloc{-1};
+bool take_forced_alloc_failure() {
+  long v = g_fail_alloc.load();
+  while (v >= 0) {
+    if (g_fail_alloc.compare_exchange_weak(v, v - 1)) return v == 0;
+  }
+  return false;
+}
 void set_tuning(int splits, int qpw, int cap) {
   g_splits = splits;
   g_qpw = qpw;
@@ -115,9 +126,9 @@ gv_status alloc_model(int C, int d, int D, gv_model** out) {
   m->fitted = false;
   m->iters = 0;
   if (hipGetDevice(&m->device) != hipSuccess) m->device = 0;
-  hipError_t e1 = hipMalloc(&m->mu, sizeof(double) * C * D);
-  hipError_t e2 = hipMalloc(&m->A, sizeof(double) * C * d * D);
-  hipError_t e3 = hipMalloc(&m->B, sizeof(double) * C * d * D);
+  hipError_t e1 = dev_malloc(&m->mu, sizeof(double) * C * D);
+  hipError_t e2 = dev_malloc(&m->A, sizeof(double) * C * d * D);
+  hipError_t e3 = dev_malloc(&m->B, sizeof(double) * C * d * D);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
     gv_model_destroy(m);
     set_error("device allocation of the model failed");
@@ -133,7 +144,7 @@ bool valid(const gv_model* m) { return valid_model(m); }
 
 gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite) {
   int* flag = nullptr;
-  GV_HIP(hipMallocAsync((void**)&flag, sizeof(int), st));
+  GV_HIP(dev_malloc_async((void**)&flag, sizeof(int), st));
   GV_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
   if (count > 0) {
     int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
@@ -313,15 +324,15 @@ gv_status gv_encode(const gv_model* model, const float* X, int64_t n, gv_format 
       return s;
     };
     x->n_pad = 0;
-    if (hipMalloc(&x->tags, n) != hipSuccess || hipMalloc(&x->offsets, sizeof(int64_t) * (x->C + 1)) != hipSuccess ||
-        hipMalloc(&x->seg_end, sizeof(int64_t) * x->C) != hipSuccess ||
-        hipMalloc(&x->scale, sizeof(float) * x->C) != hipSuccess) {
+    if (dev_malloc(&x->tags, n) != hipSuccess || dev_malloc(&x->offsets, sizeof(int64_t) * (x->C + 1)) != hipSuccess ||
+        dev_malloc(&x->seg_end, sizeof(int64_t) * x->C) != hipSuccess ||
+        dev_malloc(&x->scale, sizeof(float) * x->C) != hipSuccess) {
       set_error("gv_encode: device allocation failed");
       return fail(GV_ENOMEM);
     }
     if (x->own_X) {
       float* copy = nullptr;
-      if (hipMalloc(&copy, sizeof(float) * n * x->D) != hipSuccess) {
+      if (dev_malloc(&copy, sizeof(float) * n * x->D) != hipSuccess) {
         set_error("gv_encode: device allocation of the X copy failed");
         return fail(GV_ENOMEM);
       }
@@ -397,10 +408,10 @@ gv_status gv_index_reproject(const gv_model* old_model, const gv_model* new_mode
       gv_index_destroy(x);
       return s;
     };
-    if (hipMalloc(&x->tags, std::max<int64_t>(x->n, 1)) != hipSuccess ||
-        hipMalloc(&x->offsets, sizeof(int64_t) * (C + 1)) != hipSuccess ||
-        hipMalloc(&x->seg_end, sizeof(int64_t) * C) != hipSuccess ||
-        hipMalloc(&x->scale, sizeof(float) * C) != hipSuccess) {
+    if (dev_malloc(&x->tags, std::max<int64_t>(x->n, 1)) != hipSuccess ||
+        dev_malloc(&x->offsets, sizeof(int64_t) * (C + 1)) != hipSuccess ||
+        dev_malloc(&x->seg_end, sizeof(int64_t) * C) != hipSuccess ||
+        dev_malloc(&x->scale, sizeof(float) * C) != hipSuccess) {
       set_error("gv_index_reproject: device allocation failed");
       return fail(GV_ENOMEM);
     }
@@ -601,7 +612,7 @@ gv_status gv_search(const gv_model* model, const gv_index* index, const float* Q
     SearchPlan plan;
     GV_TRY(search_plan(model, index, m, kappa, &plan));
     void* ws = nullptr;
-    GV_HIP(hipMallocAsync(&ws, plan.bytes, st));
+    GV_HIP(dev_malloc_async(&ws, plan.bytes, st));
     const gv_status s = search_run(model, index, Q, m, k, kappa, out_ids, out_scores, plan, ws, st);
     (void)hipFreeAsync(ws, st);
     return s;
@@ -693,7 +704,7 @@ gv_status gv_search_flex(const gv_model* model, const gv_index* index, const flo
     SearchPlan plan;
     GV_TRY(search_plan(model, index, m, kappa, &plan, d_search, rerank == GV_RERANK_STORED));
     void* ws = nullptr;
-    GV_HIP(hipMallocAsync(&ws, plan.bytes, st));
+    GV_HIP(dev_malloc_async(&ws, plan.bytes, st));
     const gv_status s = search_run(model, index, Q, m, k, kappa, out_ids, out_scores, plan, ws, st);
     (void)hipFreeAsync(ws, st);
     return s;
@@ -795,7 +806,7 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
     GV_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     const size_t qbytes = batched_queue_bytes((int)ent.size());
     void* ws = nullptr;
-    GV_HIP(hipMalloc(&ws, ws_bytes + qbytes));
+    GV_HIP(dev_malloc(&ws, ws_bytes + qbytes));
     for (BatchEntry& b : ent) b.ws = (uint8_t*)ws + (uintptr_t)b.ws;
     uint8_t* qmem = (uint8_t*)ws + ws_bytes;
     // capture: projections and cascades as branches, the full scans of all
@@ -872,6 +883,18 @@ gv_status gv_scan_plan(int64_t n, int64_t n_pad, int32_t C, gv_format fmt, int32
     return GV_OK;
   });
 }
+
+gv_status gv_debug_fail_alloc(int32_t after) {
+  clear_error();
+  if (after < -1) {
+    set_error("gv_debug_fail_alloc: after must be -1 or non-negative");
+    return GV_EINVAL;
+  }
+  g_fail_alloc = after;
+  return GV_OK;
+}
+
+int32_t gv_debug_allocs_pending(void) { return (int32_t)std::max(-1L, g_fail_alloc.load()); }
 
 gv_status gv_search_optimism(int32_t rank) {
   clear_error();

@@ -30,6 +30,40 @@ void clear_error();
     }                                                                      \
   } while (0)
 
+// Every device allocation of the library goes through dev_malloc /
+// dev_malloc_async, so that a test can make one chosen allocation fail as if
+// the device were out of memory (gv_debug_fail_alloc).
+bool take_forced_alloc_failure();
+template <typename T>
+inline hipError_t dev_malloc(T** p, size_t bytes) {
+  if (take_forced_alloc_failure()) return hipErrorOutOfMemory;
+  return hipMalloc((void**)p, bytes);
+}
+template <typename T>
+inline hipError_t dev_malloc_async(T** p, size_t bytes, hipStream_t st) {
+  if (take_forced_alloc_failure()) return hipErrorOutOfMemory;
+  return hipMallocAsync((void**)p, bytes, st);
+}
+// A stream-ordered temporary, freed on its stream when the guard leaves scope
+// (error returns included); release() hands it to the caller instead.
+template <typename T>
+struct TempBuf {
+  T* p = nullptr;
+  hipStream_t st;
+  explicit TempBuf(hipStream_t s) : st(s) {}
+  TempBuf(const TempBuf&) = delete;
+  TempBuf& operator=(const TempBuf&) = delete;
+  hipError_t alloc(size_t bytes) { return dev_malloc_async(&p, bytes > 0 ? bytes : 1, st); }
+  T* release() {
+    T* q = p;
+    p = nullptr;
+    return q;
+  }
+  ~TempBuf() {
+    if (p) (void)hipFreeAsync(p, st);
+  }
+};
+
 #define GV_TRY(...)                     \
   do {                                  \
     gv_status _s = (__VA_ARGS__);       \

@@ -129,8 +129,9 @@ __global__ void k_quantize(const float* __restrict__ v, int64_t n_pad, int d, in
 gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* tags, hipStream_t st) {
   const int C = model->C, D = model->D;
   const int64_t chunk = std::min<int64_t>(n, 1 << 20);
-  double* dots = nullptr;
-  GV_HIP(hipMallocAsync((void**)&dots, sizeof(double) * chunk * C, st));
+  TempBuf<double> dbuf(st);
+  GV_HIP(dbuf.alloc(sizeof(double) * chunk * C));
+  double* dots = dbuf.p;
   gv_status s = GV_OK;
   for (int64_t s0 = 0; s0 < n && s == GV_OK; s0 += chunk) {
     const int64_t rows = std::min(chunk, n - s0);
@@ -141,7 +142,6 @@ gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* t
       hipLaunchKernelGGL(k_argmax_u8, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, dots, rows, C,
                          tags + s0);
   }
-  GV_HIP(hipFreeAsync(dots, st));
   GV_TRY(s);
   GV_HIP(hipGetLastError());
   return GV_OK;
@@ -154,11 +154,12 @@ gv_status tags_impl(const gv_model* model, const float* X, int64_t n, uint8_t* t
 // of the stored rows (-1 padding), to be freed by the caller with hipFreeAsync.
 gv_status group_rows(int64_t n, int C, int dp, int fmt, hipStream_t st, gv_index* idx, int64_t** ids64_out) {
   const int64_t nb = (n + kBlockRows - 1) / kBlockRows;
-  int64_t* ids64 = nullptr;
-  int32_t* hist = nullptr;
-  int64_t* base = nullptr;
-  GV_HIP(hipMallocAsync((void**)&hist, sizeof(int32_t) * nb * C, st));
-  GV_HIP(hipMallocAsync((void**)&base, sizeof(int64_t) * nb * C, st));
+  TempBuf<int32_t> hbuf(st);
+  TempBuf<int64_t> bbuf(st), ibuf(st);
+  GV_HIP(hbuf.alloc(sizeof(int32_t) * nb * C));
+  GV_HIP(bbuf.alloc(sizeof(int64_t) * nb * C));
+  int32_t* hist = hbuf.p;
+  int64_t* base = bbuf.p;
   hipLaunchKernelGGL(k_block_hist, dim3((unsigned)nb), dim3(256), 0, st, idx->tags, n, C, hist);
   GV_HIP(hipGetLastError());
   std::vector<int32_t> h_hist((size_t)nb * C);
@@ -182,10 +183,11 @@ gv_status group_rows(int64_t n, int C, int dp, int fmt, hipStream_t st, gv_index
   idx->h_offsets[C] = run;
   idx->n_pad = run;
   idx->n_rows = rows;
-  GV_HIP(hipMalloc((void**)&idx->ids, sizeof(int32_t) * std::max<int64_t>(run, 1)));
-  GV_HIP(hipMalloc((void**)&idx->pos, sizeof(int32_t) * std::max<int64_t>(n, 1)));
-  GV_HIP(hipMalloc(&idx->xlow, (size_t)std::max<int64_t>(run, 1) * dp * fmt_bytes(fmt)));
-  GV_HIP(hipMallocAsync((void**)&ids64, sizeof(int64_t) * std::max<int64_t>(run, 1), st));
+  GV_HIP(dev_malloc((void**)&idx->ids, sizeof(int32_t) * std::max<int64_t>(run, 1)));
+  GV_HIP(dev_malloc((void**)&idx->pos, sizeof(int32_t) * std::max<int64_t>(n, 1)));
+  GV_HIP(dev_malloc(&idx->xlow, (size_t)std::max<int64_t>(run, 1) * dp * fmt_bytes(fmt)));
+  GV_HIP(ibuf.alloc(sizeof(int64_t) * std::max<int64_t>(run, 1)));
+  int64_t* ids64 = ibuf.p;
   GV_HIP(hipMemsetAsync(idx->ids, 0xFF, sizeof(int32_t) * run, st));   // -1: padding
   GV_HIP(hipMemsetAsync(ids64, 0xFF, sizeof(int64_t) * run, st));
   GV_HIP(hipMemcpyAsync(base, h_base.data(), sizeof(int64_t) * nb * C, hipMemcpyHostToDevice, st));
@@ -196,10 +198,8 @@ gv_status group_rows(int64_t n, int C, int dp, int fmt, hipStream_t st, gv_index
   hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nb), dim3(64), 0, st, idx->tags, n, C, base, nb, idx->ids, ids64,
                      idx->pos);
   GV_HIP(hipGetLastError());
-  GV_HIP(hipFreeAsync(hist, st));
-  GV_HIP(hipFreeAsync(base, st));
   GV_HIP(hipStreamSynchronize(st));  // the host staging vectors end with this block
-  *ids64_out = ids64;
+  *ids64_out = ibuf.release();
   return GV_OK;
 }
 
@@ -208,8 +208,9 @@ gv_status group_rows(int64_t n, int C, int dp, int fmt, hipStream_t st, gv_index
 gv_status quantize_rows(const float* v, int d, int fmt, hipStream_t st, gv_index* idx) {
   const int C = idx->C, dp = idx->dp;
   const int64_t n_pad = idx->n_pad;
-  uint32_t* amax = nullptr;
-  GV_HIP(hipMallocAsync((void**)&amax, sizeof(uint32_t) * C, st));
+  TempBuf<uint32_t> abuf(st);
+  GV_HIP(abuf.alloc(sizeof(uint32_t) * C));
+  uint32_t* amax = abuf.p;
   GV_HIP(hipMemsetAsync(amax, 0, sizeof(uint32_t) * C, st));
   hipLaunchKernelGGL(k_segment_amax, dim3(64, C), dim3(256), 0, st, v, d, idx->offsets, amax);
   GV_HIP(hipGetLastError());
@@ -244,7 +245,6 @@ gv_status quantize_rows(const float* v, int d, int fmt, hipStream_t st, gv_index
       break;
   }
   GV_HIP(hipGetLastError());
-  GV_HIP(hipFreeAsync(amax, st));
   GV_HIP(hipStreamSynchronize(st));
   return GV_OK;
 }
@@ -256,13 +256,15 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
   GV_TRY(tags_impl(model, X, n, idx->tags, st));
 
   // ------------------------------------------------ stable grouping by tag, padded segments
-  int64_t* ids64 = nullptr;
-  GV_TRY(group_rows(n, C, dp, fmt, st, idx, &ids64));
+  TempBuf<int64_t> ibuf(st);
+  GV_TRY(group_rows(n, C, dp, fmt, st, idx, &ibuf.p));
+  const int64_t* ids64 = ibuf.p;
   const int64_t n_pad = idx->n_pad;
 
   // ------------------------------------------------ x_low = fl32(B_c x), FP64 accumulation (Eq. 10)
-  float* v = nullptr;
-  GV_HIP(hipMallocAsync((void**)&v, sizeof(float) * std::max<int64_t>(n_pad, 1) * d, st));
+  TempBuf<float> vbuf(st);
+  GV_HIP(vbuf.alloc(sizeof(float) * std::max<int64_t>(n_pad, 1) * d));
+  float* v = vbuf.p;
   GV_HIP(hipMemsetAsync(v, 0, sizeof(float) * n_pad * d, st));
   for (int c = 0; c < C; ++c) {
     const int64_t a = idx->h_offsets[c], nc = idx->h_counts[c];
@@ -274,8 +276,6 @@ gv_status encode_impl(const gv_model* model, const float* X, int64_t n, int fmt,
 
   // ------------------------------------------------ per-cluster scale and quantisation
   GV_TRY(quantize_rows(v, d, fmt, st, idx));
-  GV_HIP(hipFreeAsync(v, st));
-  GV_HIP(hipFreeAsync(ids64, st));
   GV_HIP(hipStreamSynchronize(st));
   return GV_OK;
 }

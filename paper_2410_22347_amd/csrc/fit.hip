@@ -44,7 +44,7 @@ struct DevBuf {
   T* p = nullptr;
   gv_status alloc(size_t count) {
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    hipError_t e = dev_malloc(&p, count * sizeof(T));
     if (e != hipSuccess) {
       p = nullptr;
       set_error(std::string("hipMalloc: ") + hipGetErrorString(e));

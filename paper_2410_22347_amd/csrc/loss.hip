@@ -76,7 +76,7 @@ struct Scratch {
   hipStream_t st;
   explicit Scratch(hipStream_t s) : st(s) {}
   gv_status alloc(size_t count) {
-    if (hipMallocAsync((void**)&p, sizeof(T) * std::max<size_t>(count, 1), st) != hipSuccess) {
+    if (dev_malloc_async((void**)&p, sizeof(T) * std::max<size_t>(count, 1), st) != hipSuccess) {
       set_error("loss scratch allocation failed");
       return GV_ENOMEM;
     }

@@ -86,8 +86,9 @@ gv_status reproject_impl(const gv_model* m0, const gv_model* m1, const gv_index*
   GV_HIP(hipGetLastError());
 
   // ------------------------------------------------ grouping (old rows first in each segment: smaller ids)
-  int64_t* ids64 = nullptr;
-  GV_TRY(group_rows(n, C, out->dp, fmt, st, out, &ids64));
+  TempBuf<int64_t> ibuf(st);
+  GV_TRY(group_rows(n, C, out->dp, fmt, st, out, &ibuf.p));
+  const int64_t* ids64 = ibuf.p;
   std::vector<uint8_t> h_tags(n);
   GV_HIP(hipMemcpyAsync(h_tags.data(), out->tags, n, hipMemcpyDeviceToHost, st));
   GV_HIP(hipStreamSynchronize(st));
@@ -96,14 +97,17 @@ gv_status reproject_impl(const gv_model* m0, const gv_model* m1, const gv_index*
     if (h_tags[i] < C) ++old_cnt[h_tags[i]];
 
   // ------------------------------------------------ T_c = B'_c A_c^T (D x D per cluster, FP64)
-  double* T = nullptr;
-  float* Y = nullptr;
-  float* v = nullptr;
-  int64_t* src = nullptr;
-  GV_HIP(hipMallocAsync((void**)&T, sizeof(double) * DD * C, st));
-  GV_HIP(hipMallocAsync((void**)&Y, sizeof(float) * std::max<int64_t>(in->n_pad, 1) * d, st));
-  GV_HIP(hipMallocAsync((void**)&v, sizeof(float) * std::max<int64_t>(out->n_pad, 1) * d, st));
-  GV_HIP(hipMallocAsync((void**)&src, sizeof(int64_t) * std::max<int64_t>(out->n_pad, 1), st));
+  TempBuf<double> tbuf(st);
+  TempBuf<float> ybuf(st), vbuf(st);
+  TempBuf<int64_t> sbuf(st);
+  GV_HIP(tbuf.alloc(sizeof(double) * DD * C));
+  GV_HIP(ybuf.alloc(sizeof(float) * std::max<int64_t>(in->n_pad, 1) * d));
+  GV_HIP(vbuf.alloc(sizeof(float) * std::max<int64_t>(out->n_pad, 1) * d));
+  GV_HIP(sbuf.alloc(sizeof(int64_t) * std::max<int64_t>(out->n_pad, 1)));
+  double* T = tbuf.p;
+  float* Y = ybuf.p;
+  float* v = vbuf.p;
+  int64_t* src = sbuf.p;
   GV_HIP(hipMemsetAsync(v, 0, sizeof(float) * out->n_pad * d, st));
   {
     GemmOperand<double> b1{m1->B, D, nullptr, Layout::RowMajor, (int64_t)DD};
@@ -138,11 +142,6 @@ gv_status reproject_impl(const gv_model* m0, const gv_model* m1, const gv_index*
   }
   // ------------------------------------------------ per-cluster scale and storage
   GV_TRY(quantize_rows(v, d, fmt, st, out));
-  GV_HIP(hipFreeAsync(T, st));
-  GV_HIP(hipFreeAsync(Y, st));
-  GV_HIP(hipFreeAsync(v, st));
-  GV_HIP(hipFreeAsync(src, st));
-  GV_HIP(hipFreeAsync(ids64, st));
   GV_HIP(hipStreamSynchronize(st));
   return GV_OK;
 }

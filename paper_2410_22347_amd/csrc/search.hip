@@ -66,10 +66,10 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
                        hipStream_t st, int d_search) {
   const int C = model->C, d = model->d, D = model->D, dp = pad_dim(d);
   const int ds = d_search > 0 ? d_search : d, dpo = pad_dim(ds);
-  float* tmp = nullptr;
+  TempBuf<float> tmp(st);
   if (!qc) {
-    GV_HIP(hipMallocAsync((void**)&tmp, sizeof(float) * m * C * dp, st));
-    qc = tmp;
+    GV_HIP(tmp.alloc(sizeof(float) * m * C * dp));
+    qc = tmp.p;
   }
   // q_c = fl32(A_c q), FP64 accumulation; columns j of the stacked A map to (c, j % d)
   gv_status s = GV_OK;
@@ -93,7 +93,6 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
       default: hipLaunchKernelGGL(k_quant_queries<GV_BF16>, dim3(grid), dim3(256), 0, st, qc, m, C, d, dp, ds, dpo, T, t, qhat); break;
     }
   }
-  if (tmp) GV_HIP(hipFreeAsync(tmp, st));
   GV_TRY(s);
   GV_HIP(hipGetLastError());
   return GV_OK;
@@ -808,7 +807,7 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
   ScanPlan p;
   GV_TRY(plan_scan(idx, m, kappa, &p, d_search));
   uint8_t* ws = nullptr;
-  if (hipMallocAsync((void**)&ws, std::max<size_t>(p.bytes, 256), st) != hipSuccess) {
+  if (dev_malloc_async((void**)&ws, std::max<size_t>(p.bytes, 256), st) != hipSuccess) {
     set_error("search scratch allocation failed");
     return GV_ENOMEM;
   }
@@ -890,7 +889,7 @@ gv_status search_lazy_impl(const gv_model* model, const gv_index* idx, const flo
   const size_t off_cand = align256(p.bytes), off_csc = align256(off_cand + sizeof(int32_t) * m * kappa);
   const size_t bytes = align256(off_csc + sizeof(float) * m * kappa);
   uint8_t* ws = nullptr;
-  if (hipMallocAsync((void**)&ws, bytes, st) != hipSuccess) {
+  if (dev_malloc_async((void**)&ws, bytes, st) != hipSuccess) {
     set_error("search scratch allocation failed");
     return GV_ENOMEM;
   }

@@ -108,10 +108,12 @@ gv_status gv_autotune(const gv_model* model, const gv_index* index, const float*
       for (int splits : {0, 16, 64, 256, 1024}) cand.push_back(Tuning{splits, qpw, 0});
     for (int cap : {768, 1024}) cand.push_back(Tuning{0, 0, cap});
     const int s0 = tuned_splits(), q0 = tuned_qpw(), c0 = tuned_cap();
-    int32_t* ids = nullptr;
-    float* sc = nullptr;
-    GV_HIP(hipMalloc((void**)&ids, sizeof(int32_t) * m * k));
-    GV_HIP(hipMalloc((void**)&sc, sizeof(float) * m * k));
+    TempBuf<int32_t> ibuf(st);
+    TempBuf<float> sbuf(st);
+    GV_HIP(ibuf.alloc(sizeof(int32_t) * m * k));
+    GV_HIP(sbuf.alloc(sizeof(float) * m * k));
+    int32_t* ids = ibuf.p;
+    float* sc = sbuf.p;
     hipEvent_t e0, e1;
     GV_HIP(hipEventCreate(&e0));
     GV_HIP(hipEventCreate(&e1));
@@ -126,7 +128,7 @@ gv_status gv_autotune(const gv_model* model, const gv_index* index, const float*
       SearchPlan plan;
       if (search_plan(model, index, m, kappa, &plan) != GV_OK) continue;
       void* ws = nullptr;
-      if (hipMalloc(&ws, plan.bytes) != hipSuccess) continue;
+      if (dev_malloc(&ws, plan.bytes) != hipSuccess) continue;
       gv_status r = search_run(model, index, Q, m, k, kappa, ids, sc, plan, ws, st);  // warm-up
       if (r == GV_OK && hipEventRecord(e0, st) == hipSuccess) {
         for (int i = 0; i < reps && r == GV_OK; ++i) r = search_run(model, index, Q, m, k, kappa, ids, sc, plan, ws, st);
@@ -154,8 +156,6 @@ gv_status gv_autotune(const gv_model* model, const gv_index* index, const float*
     set_tuning(s0, q0, c0);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipFree(ids);
-    (void)hipFree(sc);
     GV_TRY(s);
     if (tried == 0) {
       set_error("gv_autotune: no candidate launch shape could run this search");
