@@ -103,14 +103,26 @@ __global__ void k_argmax(const double* __restrict__ dots, int64_t rows, int C, i
   out[r] = best;
 }
 
-// S[c][j] = sum over members r of cluster c (in grouped order) of Xt[perm[r]][j]
-__global__ void k_cluster_sums(const double* __restrict__ Xt, int D, const int64_t* __restrict__ perm,
-                               const int64_t* __restrict__ off, double* __restrict__ S) {
+// Cluster sums in two deterministic passes.  Pass 1: part[c][k][j] = sum of
+// Xt[perm[r]][j] over the k-th run of kSumRun members of cluster c (grouped
+// order).  Pass 2: S[c][j] = sum over k of part[c][k][j], in order of k.
+constexpr int kSumRun = 256;
+__global__ void k_cluster_part_sums(const double* __restrict__ Xt, int D, const int64_t* __restrict__ perm,
+                                    const int64_t* __restrict__ off, int runs, double* __restrict__ part) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.z, k = blockIdx.y;
+  if (j >= D) return;
+  const int64_t r0 = off[c] + (int64_t)k * kSumRun, r1 = std::min<int64_t>(off[c + 1], r0 + kSumRun);
+  double s = 0.0;
+  for (int64_t r = r0; r < r1; ++r) s += Xt[perm[r] * D + j];
+  part[((int64_t)c * runs + k) * D + j] = s;
+}
+__global__ void k_cluster_sums(const double* __restrict__ part, int D, int runs, double* __restrict__ S) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (j >= D) return;
   double s = 0.0;
-  for (int64_t r = off[c]; r < off[c + 1]; ++r) s += Xt[perm[r] * D + j];
+  for (int k = 0; k < runs; ++k) s += part[((int64_t)c * runs + k) * D + j];
   S[(int64_t)c * D + j] = s;
 }
 
@@ -388,8 +400,18 @@ gv_status fit_impl(const float* X, int64_t n, const float* Q, int64_t m, int D, 
     counting_sort(a, C, perm, off);
     GV_HIP(hipMemcpyAsync(d_perm.p, perm.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, st));
     GV_HIP(hipMemcpyAsync(d_off.p, off.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_cluster_sums, dim3((D + 127) / 128, C), dim3(128), 0, st, Xt.p, D, d_perm.p, d_off.p, S.p);
-    GV_HIP(hipGetLastError());
+    {
+      int64_t largest = 0;
+      for (int c = 0; c < C; ++c) largest = std::max<int64_t>(largest, off[c + 1] - off[c]);
+      const int runs = (int)std::max<int64_t>(1, (largest + kSumRun - 1) / kSumRun);
+      DevBuf<double> part;
+      GV_TRY(part.alloc((size_t)C * runs * D));
+      hipLaunchKernelGGL(k_cluster_part_sums, dim3((D + 127) / 128, runs, C), dim3(128), 0, st, Xt.p, D, d_perm.p,
+                         d_off.p, runs, part.p);
+      hipLaunchKernelGGL(k_cluster_sums, dim3((D + 127) / 128, C), dim3(128), 0, st, part.p, D, runs, S.p);
+      GV_HIP(hipGetLastError());
+      GV_HIP(hipStreamSynchronize(st));  // part is freed (synchronously) at the end of this block
+    }
     GV_HIP(hipMemcpyAsync(h_S.data(), S.p, sizeof(double) * C * D, hipMemcpyDeviceToHost, st));
     GV_HIP(hipStreamSynchronize(st));
     for (int c = 0; c < C; ++c) {
