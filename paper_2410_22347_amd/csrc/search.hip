@@ -347,8 +347,12 @@ __global__ __launch_bounds__(256) void k_select(const uint64_t* __restrict__ buf
   }
 
   if (!FINAL) {
-    if (kept < kappa) {  // fewer than kappa candidates: no bound
-      if (seed_opt && tid == 0) seed_opt[q] = seed[q];
+    if (kept < kappa) {  // fewer than kappa candidates: no exact kappa-th best
+      // all the level's candidates are kept: the kappa_opt-th best is exact when
+      // there are that many
+      float opt = -INFINITY;
+      if (seed_opt && kept >= kappa_opt) opt = key_score(block_kth(keys, kept, kappa_opt, sel));
+      if (seed_opt && tid == 0) seed_opt[q] = fmaxf(seed[q], opt);
       return;
     }
     // the kappa-th best is the smallest kept key
@@ -496,7 +500,8 @@ struct ScanPlan {
   // of the last sample level, and a repair pass rescans the rare queries for
   // which it kept fewer than kappa keys (see run_scan)
   bool optimistic = false;
-  int kappa_opt = 0;
+  int kappa_opt = 0;                 // rank of the full scan's optimistic seed
+  std::vector<int> next_rank;        // per level: rank of the optimistic seed it gives the next level
   size_t off_buf = 0, off_cnt = 0, off_seed = 0, off_dense = 0, off_seed_opt = 0, off_rescan = 0, bytes = 0;
 };
 
@@ -599,14 +604,29 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
   // kappa keys leaves the exact seed of the level before in place.
   p->optimistic = false;
   p->kappa_opt = 0;
-  const size_t nl = p->levels.size();
+  p->next_rank.assign(p->levels.size(), 0);
   const int ov = tuned_optimism();
+  const size_t nl = p->levels.size();
   if (nl >= 3 && ov >= 0) {
-    const double mu = (double)kappa * (double)p->levels[nl - 1] / (double)p->levels[nl - 2];
-    const int ko = ov > 0 ? ov : (int)std::ceil(mu + 6.0 * std::sqrt(mu) + 6.0);
+    // the rank whose score, taken in a sample of fraction f of the next level,
+    // leaves at least `need` rows of that level above it (six standard deviations)
+    auto rank_for = [&](int need, size_t li) {
+      const double mu = (double)need * (double)p->levels[li + 1] / (double)p->levels[li];
+      return ov > 0 ? ov : (int)std::ceil(mu + 6.0 * std::sqrt(mu) + 6.0);
+    };
+    const int ko = rank_for(kappa, nl - 2);
     if (ko < kappa) {
       p->optimistic = true;
       p->kappa_opt = ko;
+      // the level before the full scan gives it rank ko; an earlier sample level
+      // only needs its successor to keep the rank that successor passes on
+      int need = ko;
+      p->next_rank[nl - 2] = ko;
+      for (size_t li = nl - 2; li-- > 1;) {  // filtering sample levels (level 0 is the dense sample)
+        const int r = std::min(rank_for(need, li), kappa);
+        p->next_rank[li] = r;
+        need = r;
+      }
     }
   }
   const uint64_t keys = (uint64_t)m * p->Rmax * p->cap;
@@ -758,7 +778,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
       // a sample level also yields the optimistic seed of the next level
       hipLaunchKernelGGL(k_select<false>, dim3((unsigned)m), dim3(256), 0, st, buf, cnt, sh.R, p.cap, kappa,
                          idx->ids, seed, (int32_t*)nullptr, (float*)nullptr, p.optimistic ? seed_opt : (float*)nullptr,
-                         p.kappa_opt);
+                         p.next_rank[li]);
     }
   }
   GV_TRY(s);
