@@ -8,8 +8,8 @@
 // second moments (sum over rows of x x^T), the reduced vectors B_c x and the
 // eager query views A_c q.
 //
-// Tiling: a 256-thread workgroup owns a 64 x 64 or 128 x 128 output tile; its
-// four wavefronts each own a quarter.  K advances in steps of 32 through LDS,
+// Tiling: a 256-thread workgroup owns a 64 x 64 output tile; its four
+// wavefronts each own a 32 x 32 quarter.  K advances in steps of 32 through LDS,
 // stored k-major so every MFMA operand read is a contiguous 16-element row.
 // The next step's operands are loaded into registers while the matrix core
 // works on the current one.
@@ -29,9 +29,7 @@ __device__ inline double ld_elem(const T* p, int64_t idx) {
 
 // Tile shapes: a 256-thread workgroup owns a TM x TN output tile, each of its
 // four wavefronts a (TM / 2) x (TN / 2) quarter of (TM / 32) x (TN / 32) blocks
-// of 16 x 16.  64 x 64 for small problems; 128 x 128 for large ones, which
-// halves the operand traffic per flop (each slab element feeds twice the
-// matrix-core work).
+// of 16 x 16.
 template <int TM_, int TN_>
 struct Tile {
   static constexpr int TM = TM_, TN = TN_, LDSP = (TM > TN ? TM : TN) + 2;
@@ -184,18 +182,16 @@ template <typename TA, typename TB>
 gv_status gemm_f64(int64_t M, int64_t N, int64_t K, GemmOperand<TA> a, GemmOperand<TB> b, Epi epi,
                    GemmOut out, hipStream_t st, int batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return GV_OK;
-  // the large tile once both sides span several of them and the grid still
-  // fills the device twice over
-  const bool big = M >= 256 && N >= 256 && ((M + 127) / 128) * ((N + 127) / 128) * batch >= 512;
-  const int tm = big ? 128 : 64, tn = big ? 128 : 64;
-  int64_t gx = (M + tm - 1) / tm, gy = (N + tn - 1) / tn;
+  // 64 x 64 tiles: 128 x 128 tiles (half the operand traffic per flop) measured
+  // slower on the S1 product at m = 4096 (1.08 against 0.91 ms)
+  using TL = Tile<64, 64>;
+  int64_t gx = (M + TL::TM - 1) / TL::TM, gy = (N + TL::TN - 1) / TL::TN;
   if (gy > 65535 || batch > 65535) {
     set_error("gemm_f64: N or batch too large");
     return GV_EINVAL;
   }
   dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)batch);
-  if (big) launch<TA, TB, Tile<128, 128>>(M, N, K, a, b, epi, out, st, grid);
-  else launch<TA, TB, Tile<64, 64>>(M, N, K, a, b, epi, out, st, grid);
+  launch<TA, TB, TL>(M, N, K, a, b, epi, out, st, grid);
   GV_HIP(hipGetLastError());
   return GV_OK;
 }

@@ -197,14 +197,14 @@ def test_project_matches_oracle(gv, fmt, m):
         assert np.all(tb > 0)
 
 
-def test_project_large_tiles_matches_oracle(gv):
-    """S1 for a batch large enough for the 128 x 128 FP64 matrix-core tiles
-    (6600 queries x 8 clusters x 160 rows): q_c equals the oracle's fl32 of the
-    FP64 product wherever FP64 summation order cannot flip the rounding, and is
-    within one FP32 ulp everywhere."""
+def test_project_large_batch_matches_oracle(gv):
+    """S1 for a large batch (6600 queries x 8 clusters x 160 rows, a grid of many
+    FP64 matrix-core tiles): q_c equals the oracle's fl32 of the FP64 product
+    wherever FP64 summation order cannot flip the rounding, and is within one
+    FP32 ulp everywhere."""
     cfg, D, J, n, ml, d, C, _, kappa = CASES["d160-C8"]
     m = 6600
-    _say(f"[project large tiles] m{m}")
+    _say(f"[project large batch] m{m}")
     X, QL, Q = problem(cfg, D, J, n, ml, m)
     om = oracle_model(cfg, D, J, n, ml, d, C, 7)
     model = gv.model_import(om.mu, om.A, om.B)
