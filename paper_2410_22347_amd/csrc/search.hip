@@ -140,17 +140,15 @@ __global__ void k_seed_init(int64_t m, float* __restrict__ seed) {
 // it, relatively), found from two 11-bit histograms: two passes over the row
 // instead of the four or more of an exact radix select.
 constexpr int kBoundBins = 2048;
-__global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ dense, int64_t m, int64_t ns,
-                                                      int kappa, float* __restrict__ seed) {
-  __shared__ uint32_t hist[4][kBoundBins];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
-  if (q >= m) return;
-  const float* row = dense + q * ns;
-  uint32_t* h = hist[wave];
+
+// the bound above for rank `rank` of the ns scores of one row (one wavefront;
+// h: kBoundBins words of its LDS); -inf when the row holds fewer than rank
+// finite scores
+__device__ float dense_rank_bound(const float* __restrict__ row, int64_t ns, uint32_t rank, uint32_t* h) {
+  const int lane = threadIdx.x & 63;
   constexpr int kUn = 8;  // loads in flight per lane
   int valid = 0;
-  uint32_t prefix = 0, need = (uint32_t)kappa;
+  uint32_t prefix = 0, need = rank;
   for (int pass = 0; pass < 2; ++pass) {
     const int shift = pass == 0 ? 21 : 10;
     const uint32_t mask = pass == 0 ? 0u : 0xFFE00000u;
@@ -169,7 +167,10 @@ __global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ 
     }
     if (pass == 0) {
       for (int o = 32; o > 0; o >>= 1) valid += __shfl_xor(valid, o);
-      if (valid < kappa) return;  // fewer than kappa scores: no bound
+      if (valid < (int)rank) {  // fewer than rank scores: no bound
+        wave_sync();
+        return -INFINITY;
+      }
     }
     wave_sync();
     // lane l owns bins [32 l, 32 l + 32); keys in all higher bins, by a suffix scan
@@ -200,9 +201,27 @@ __global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ 
     prefix |= (uint32_t)digit << shift;
     wave_sync();
   }
-  float tau = unorder_f32(prefix);  // the smallest key with these 22 bits
-  if (tau != tau) tau = -INFINITY;   // a prefix below every finite score's key
-  if (lane == 0) seed[q] = fmaxf(seed[q], tau);
+  const float tau = unorder_f32(prefix);  // the smallest key with these 22 bits
+  return tau != tau ? -INFINITY : tau;    // a prefix below every finite score's key
+}
+
+// seed[q] = max(seed[q], bound of the kappa-th best); seed_opt (may be null):
+// max(seed[q], bound of the rank_opt-th best), the next level's optimistic seed
+__global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ dense, int64_t m, int64_t ns,
+                                                      int kappa, float* __restrict__ seed,
+                                                      float* __restrict__ seed_opt, int rank_opt) {
+  __shared__ uint32_t hist[4][kBoundBins];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+  if (q >= m) return;
+  const float* row = dense + q * ns;
+  const float tau = dense_rank_bound(row, ns, (uint32_t)kappa, hist[wave]);
+  const float sd = fmaxf(seed[q], tau);
+  const float opt = seed_opt ? dense_rank_bound(row, ns, (uint32_t)rank_opt, hist[wave]) : -INFINITY;
+  if (lane == 0) {
+    seed[q] = sd;
+    if (seed_opt) seed_opt[q] = fmaxf(sd, opt);
+  }
 }
 
 // ---------------------------------------------------------------------------- select
@@ -592,16 +611,16 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
   }
   if (!chosen) GV_TRY(build(tu.cap > 0 ? tu.cap : kCap, 1));
   p->ns = p->has_dense ? ((ntiles + p->levels[0] - 1) / p->levels[0]) * kRows : 0;
-  // Optimistic seeds, when the level before the full scan filters: every level
-  // after the first filtering one starts from the kappa_opt-th best score of
-  // the level before.  If a sample holds each row of the next level with
-  // probability f, the number of its rows among a query's kappa - 1 best there
-  // is about Binomial(kappa, f); the kappa_opt-th best sample score exceeds the
-  // query's kappa-th best only if that count reaches kappa_opt = f kappa +
-  // 6 sqrt(f kappa) + 6 (six standard deviations, plus room for small kappa).
-  // About kappa_opt / f keys then survive instead of kappa / f.  The full scan's
-  // repair pass keeps its result exact; a sample level that keeps fewer than
-  // kappa keys leaves the exact seed of the level before in place.
+  // Optimistic seeds, when the level before the full scan filters: every
+  // filtering level starts from a higher-ranked score of the level before.  If
+  // a sample holds each row of the next level with probability f, the number of
+  // its rows among a query's kappa - 1 best there is about Binomial(kappa, f);
+  // the kappa_opt-th best sample score exceeds the query's kappa-th best only if
+  // that count reaches kappa_opt = f kappa + 6 sqrt(f kappa) + 6 (six standard
+  // deviations, plus room for small kappa).  About kappa_opt / f keys then
+  // survive instead of kappa / f.  The full scan's repair pass keeps its result
+  // exact; a sample level that keeps fewer than kappa keys leaves the exact seed
+  // of the level before in place.
   p->optimistic = false;
   p->kappa_opt = 0;
   p->next_rank.assign(p->levels.size(), 0);
@@ -622,7 +641,7 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
       // only needs its successor to keep the rank that successor passes on
       int need = ko;
       p->next_rank[nl - 2] = ko;
-      for (size_t li = nl - 2; li-- > 1;) {  // filtering sample levels (level 0 is the dense sample)
+      for (size_t li = nl - 2; li-- > 0;) {  // earlier sample levels, the dense one (level 0) included
         const int r = std::min(rank_for(need, li), kappa);
         p->next_rank[li] = r;
         need = r;
@@ -726,10 +745,10 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     const Shape& sh = p.shapes[li];
     sh_cur = sh;
     const bool last = li + 1 == p.levels.size();
-    // levels after the first filtering one start from the optimistic seed of
-    // the level before (the full scan repairs what it misses; a sample level
-    // that keeps fewer than kappa keys leaves the exact seed as it was)
-    args.seed = li == 0 ? nullptr : (p.optimistic && li >= 2 ? seed_opt : seed);
+    // filtering levels start from the optimistic seed of the level before (the
+    // full scan repairs what it misses; a sample level that keeps fewer than
+    // kappa keys leaves the exact seed as it was)
+    args.seed = li == 0 ? nullptr : (p.optimistic ? seed_opt : seed);
     args.R = sh.R;
     args.nqb = (int)sh.nqb;
     args.stride = (int)p.levels[li];
@@ -756,7 +775,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
       s = dispatch(true);
       if (s == GV_OK)
         hipLaunchKernelGGL(k_dense_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, dense, m, p.ns, kappa,
-                           seed);
+                           seed, p.optimistic ? seed_opt : (float*)nullptr, p.next_rank[0]);
       continue;
     }
     if (sh.R > p.Rmax) {  // scratch must cover every list the launch writes
