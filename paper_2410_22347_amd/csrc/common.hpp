@@ -283,8 +283,13 @@ gv_status fit_from_stats_impl(const double* mu, const double* KQ, double m_q, co
                               const int64_t* counts, hipStream_t st, gv_model* model);
 // d_search (0: all of the model's d) is the number of leading coordinates the
 // views and the scan use (Section 3.3); q_c always holds all d of them.
+// scratch (may be null): device memory the call may overwrite, for the partial
+// products of a K-split GEMM (proj_split_bytes; allocated when missing or short)
 gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m, float* qc,
-                       float* t, void* qhat, hipStream_t st, int d_search = 0);
+                       float* t, void* qhat, hipStream_t st, int d_search = 0, void* scratch = nullptr,
+                       size_t scratch_bytes = 0);
+int proj_splits(int64_t m, int64_t rows, int K);
+size_t proj_split_bytes(int64_t m, int64_t rows, int K);
 gv_status scan_plan_describe(int64_t n, int64_t n_pad, int C, int fmt, int d, int d_search, int64_t m, int kappa,
                              gv_scan_level* levels, int max_levels, int* n_levels, int64_t* list_keys,
                              int64_t* scratch_bytes);
@@ -295,6 +300,7 @@ void keep_pool(int device);
 struct SearchPlan {
   size_t off_t = 0, off_qc = 0, off_qhat = 0, off_cand = 0, off_csc = 0, off_scan = 0, bytes = 0;
   size_t scan_bytes = 0;  // scratch of S2/S3 within the workspace (search_run re-plans and checks it)
+  size_t region_bytes = 0;  // bytes at off_scan: S2/S3's scratch, earlier S1's partial products, later S4's scores
   int d_search = 0;     // leading coordinates scanned
   bool stored = false;  // rerank from the stored vectors instead of the full-dimension X
 };
@@ -319,8 +325,11 @@ gv_status batched_run(std::vector<BatchEntry>& entries, int k, int kappa, hipStr
 size_t batched_queue_bytes(int n_entries);
 gv_status search_lazy_impl(const gv_model* model, const gv_index* idx, const float* Q, int64_t m, int k, int kappa,
                            int32_t* out_ids, float* out_scores, hipStream_t st);
+// S4; scratch (may be null): device memory the call may overwrite (dead
+// candidate lists), which lets small batches spread over more workgroups
 gv_status rerank_impl(const gv_index* index, const float* Q, int64_t m, const int32_t* cand,
-                      int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
+                      int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st,
+                      void* scratch = nullptr, size_t scratch_bytes = 0);
 gv_status rerank_stored_impl(const gv_index* index, const float* qc, int64_t m, const int32_t* cand,
                              int kappa, int k, int32_t* out_ids, float* out_scores, hipStream_t st);
 gv_status check_finite_f32(const float* p, int64_t count, hipStream_t st, bool* finite);

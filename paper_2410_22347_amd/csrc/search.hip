@@ -60,10 +60,42 @@ __global__ __launch_bounds__(256) void k_project_small(const float* __restrict__
   }
 }
 
+// S1 for batches that give the tiled GEMM few output tiles: the K loop of each
+// tile is a chain of memory latencies, so K is cut into `ks` slices computed as
+// independent products (FP64 partial tiles in scratch), then summed here in
+// slice order and rounded once to FP32.
+__global__ void k_proj_reduce(const double* __restrict__ part, int ks, int64_t m, int64_t rows, int d, int dp,
+                              int C, float* __restrict__ qc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * rows) return;
+  const int64_t i = e / rows, j = e - i * rows;
+  double v = part[e];
+  for (int z = 1; z < ks; ++z) v += part[(int64_t)z * m * rows + e];
+  const int64_t c = j / d, jj = j - c * d;
+  qc[(i * C + c) * dp + jj] = (float)v;
+}
+
 }  // namespace
 
+// K slices of S1's tiled GEMM for m queries and `rows` stacked rows of A
+// (length K): doubled while the output tiles (64 x 64) number fewer than 512
+// and K splits evenly; decided by the shape alone, so every caller of one shape
+// computes the same sums
+int proj_splits(int64_t m, int64_t rows, int K) {
+  if (m <= kSmallM) return 1;
+  const int64_t tiles = ((m + 63) / 64) * ((rows + 63) / 64);
+  int ks = 1;
+  while (ks < 16 && tiles * ks < 512 && K % (2 * ks) == 0 && K / (2 * ks) >= 32) ks *= 2;
+  return ks;
+}
+
+size_t proj_split_bytes(int64_t m, int64_t rows, int K) {
+  const int ks = proj_splits(m, rows, K);
+  return ks > 1 ? sizeof(double) * (size_t)ks * (size_t)m * (size_t)rows : 0;
+}
+
 gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m, float* qc, float* t, void* qhat,
-                       hipStream_t st, int d_search) {
+                       hipStream_t st, int d_search, void* scratch, size_t scratch_bytes) {
   const int C = model->C, d = model->d, D = model->D, dp = pad_dim(d);
   const int ds = d_search > 0 ? d_search : d, dpo = pad_dim(ds);
   TempBuf<float> tmp(st);
@@ -78,10 +110,31 @@ gv_status project_impl(const gv_model* model, int fmt, const float* Q, int64_t m
     hipLaunchKernelGGL(k_project_small, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, Q, m, D, model->A, rows,
                        d, dp, C, qc);
   } else {
+    const int64_t rows = (int64_t)C * d;
+    const int ks = proj_splits(m, rows, D);
     GemmOperand<float> qo{Q, D, nullptr, Layout::RowMajor};
     GemmOperand<double> ao{model->A, D, nullptr, Layout::RowMajor};
-    s = gemm_f64<float, double>(m, (int64_t)C * d, D, qo, ao, Epi::StoreF32Proj,
-                                GemmOut{qc, (int64_t)C * dp, d, dp, nullptr}, st);
+    if (ks == 1) {
+      s = gemm_f64<float, double>(m, rows, D, qo, ao, Epi::StoreF32Proj, GemmOut{qc, (int64_t)C * dp, d, dp, nullptr},
+                                  st);
+    } else {
+      const size_t need = proj_split_bytes(m, rows, D);
+      TempBuf<double> pbuf(st);
+      double* part = (double*)scratch;
+      if (!part || scratch_bytes < need) {
+        GV_HIP(pbuf.alloc(need));
+        part = pbuf.p;
+      }
+      const int kc = D / ks;
+      qo.bstride = kc;
+      ao.bstride = kc;
+      GemmOut po{part, rows, 0, 0, nullptr};
+      po.bstride = m * rows;
+      s = gemm_f64<float, double>(m, rows, kc, qo, ao, Epi::StoreF64, po, st, ks);
+      if (s == GV_OK)
+        hipLaunchKernelGGL(k_proj_reduce, dim3((unsigned)((m * rows + 255) / 256)), dim3(256), 0, st, part, ks, m,
+                           rows, d, dp, C, qc);
+    }
   }
   if (s == GV_OK) {
     const unsigned grid = (unsigned)((m * C + 3) / 4);
@@ -127,100 +180,126 @@ __global__ __launch_bounds__(256) void k_repair_prep(int32_t* __restrict__ cnt, 
   if (lane == 0) rescan[q] = redo ? seed[q] : INFINITY;
 }
 
-// seed[q] = -inf
-__global__ void k_seed_init(int64_t m, float* __restrict__ seed) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < m) seed[q] = -INFINITY;
-}
-
 // after the dense scan: seed = a lower bound of the kappa-th best score of the
-// sample (one wavefront per query).  Any such bound is a valid seed (at least
-// kappa rows of the next level reach it); this one is the smallest score whose
-// order key shares the top 22 bits of the kappa-th best's key (within 2^-13 of
-// it, relatively), found from two 11-bit histograms: two passes over the row
-// instead of the four or more of an exact radix select.
+// sample.  Any such bound is a valid seed (at least kappa rows of the next level
+// reach it); this one is the smallest score whose order key shares the top 22
+// bits of the kappa-th best's key (within 2^-13 of it, relatively), found from
+// two 11-bit histograms: two passes over the row instead of the four or more of
+// an exact radix select.  The optimistic seed's rank is resolved from the same
+// two passes (one first-pass histogram, a second-pass histogram per rank).
 constexpr int kBoundBins = 2048;
+constexpr int kDenseThreads = 256;
 
-// the bound above for rank `rank` of the ns scores of one row (one wavefront;
-// h: kBoundBins words of its LDS); -inf when the row holds fewer than rank
-// finite scores
-__device__ float dense_rank_bound(const float* __restrict__ row, int64_t ns, uint32_t rank, uint32_t* h) {
-  const int lane = threadIdx.x & 63;
-  constexpr int kUn = 8;  // loads in flight per lane
-  int valid = 0;
-  uint32_t prefix = 0, need = rank;
-  for (int pass = 0; pass < 2; ++pass) {
-    const int shift = pass == 0 ? 21 : 10;
-    const uint32_t mask = pass == 0 ? 0u : 0xFFE00000u;
-    for (int b = lane; b < kBoundBins; b += 64) h[b] = 0;
-    wave_sync();
-    for (int64_t i0 = lane; i0 < ns; i0 += 64 * kUn) {
-      float v[kUn];
+// the bin of h (kBoundBins counts, higher bins = larger keys) holding the
+// need-th largest key, and that key's rank within the bin; called by every
+// thread of a kDenseThreads workgroup, which returns the same result to all
+// (-1 when the bins hold fewer than need keys).  s_tot: 4 words of LDS,
+// s_out: 2 words.
+__device__ void block_rank_bin(const uint32_t* h, uint32_t need, uint32_t* s_tot, int32_t* s_out, int* digit,
+                               uint32_t* nneed) {
+  constexpr int PER = kBoundBins / kDenseThreads;  // bins per thread
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_out[0] = -1;
+  uint32_t local = 0;
 #pragma unroll
-      for (int u = 0; u < kUn; ++u) v[u] = i0 + 64 * u < ns ? row[i0 + 64 * u] : -INFINITY;
-#pragma unroll
-      for (int u = 0; u < kUn; ++u) {
-        if (pass == 0) valid += v[u] != -INFINITY;
-        const uint32_t k = order_f32(v[u]);
-        if (i0 + 64 * u < ns && (k & mask) == prefix) atomicAdd(&h[(k >> shift) & (kBoundBins - 1)], 1u);
-      }
-    }
-    if (pass == 0) {
-      for (int o = 32; o > 0; o >>= 1) valid += __shfl_xor(valid, o);
-      if (valid < (int)rank) {  // fewer than rank scores: no bound
-        wave_sync();
-        return -INFINITY;
-      }
-    }
-    wave_sync();
-    // lane l owns bins [32 l, 32 l + 32); keys in all higher bins, by a suffix scan
-    uint32_t local = 0;
-    for (int j = 0; j < 32; ++j) local += h[32 * lane + j];
-    uint32_t incl = local;  // keys in this lane's bins and all higher ones
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_down(incl, o);
-      if (lane + o < 64) incl += t;
-    }
-    uint32_t above = incl - local;
-    int digit = -1;
-    uint32_t nneed = 0;
-    if (above < need && need <= incl) {
-      for (int j = 31; j >= 0; --j) {
-        const uint32_t c = h[32 * lane + j];
-        if (above < need && need <= above + c) {
-          digit = 32 * lane + j;
-          nneed = need - above;
-        }
-        above += c;
-      }
-    }
-    const uint64_t owner = __ballot(digit >= 0);
-    const int src = __ffsll((unsigned long long)owner) - 1;
-    digit = __shfl(digit, src);
-    need = __shfl(nneed, src);
-    prefix |= (uint32_t)digit << shift;
-    wave_sync();
+  for (int j = 0; j < PER; ++j) local += h[PER * tid + j];
+  uint32_t incl = local;  // keys in this thread's bins and every higher one, within the wavefront
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_down(incl, o);
+    if (lane + o < 64) incl += t;
   }
-  const float tau = unorder_f32(prefix);  // the smallest key with these 22 bits
-  return tau != tau ? -INFINITY : tau;    // a prefix below every finite score's key
+  if (lane == 0) s_tot[wave] = incl;
+  __syncthreads();
+  for (int w = wave + 1; w < kDenseThreads / 64; ++w) incl += s_tot[w];
+  uint32_t above = incl - local;
+  if (above < need && need <= incl) {
+    for (int j = PER - 1; j >= 0; --j) {
+      const uint32_t c = h[PER * tid + j];
+      if (above < need && need <= above + c) {
+        s_out[0] = PER * tid + j;
+        s_out[1] = (int32_t)(need - above);
+      }
+      above += c;
+    }
+  }
+  __syncthreads();
+  *digit = s_out[0];
+  *nneed = (uint32_t)s_out[1];
+  __syncthreads();
 }
 
-// seed[q] = max(seed[q], bound of the kappa-th best); seed_opt (may be null):
-// max(seed[q], bound of the rank_opt-th best), the next level's optimistic seed
-__global__ __launch_bounds__(256) void k_dense_select(const float* __restrict__ dense, int64_t m, int64_t ns,
-                                                      int kappa, float* __restrict__ seed,
-                                                      float* __restrict__ seed_opt, int rank_opt) {
-  __shared__ uint32_t hist[4][kBoundBins];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+// The first seeds of a search: seed[q] = the bound of the kappa-th best;
+// seed_opt (may be null): max(seed[q], bound of the rank_opt-th best), the next
+// level's optimistic seed.  One workgroup per query; a row with fewer than a
+// rank's finite scores gives that rank no bound (-inf).
+__global__ __launch_bounds__(kDenseThreads) void k_dense_select(const float* __restrict__ dense, int64_t m,
+                                                                int64_t ns, int kappa, float* __restrict__ seed,
+                                                                float* __restrict__ seed_opt, int rank_opt) {
+  __shared__ uint32_t hist[2][kBoundBins];
+  __shared__ uint32_t s_tot[4];
+  __shared__ int32_t s_out[2];
+  __shared__ int s_valid;
+  const int tid = threadIdx.x;
+  const int64_t q = blockIdx.x;
   if (q >= m) return;
   const float* row = dense + q * ns;
-  const float tau = dense_rank_bound(row, ns, (uint32_t)kappa, hist[wave]);
-  const float sd = fmaxf(seed[q], tau);
-  const float opt = seed_opt ? dense_rank_bound(row, ns, (uint32_t)rank_opt, hist[wave]) : -INFINITY;
-  if (lane == 0) {
-    seed[q] = sd;
-    if (seed_opt) seed_opt[q] = fmaxf(sd, opt);
+  const int nr = seed_opt ? 2 : 1;
+  const uint32_t rank[2] = {(uint32_t)kappa, (uint32_t)rank_opt};
+  constexpr int kUn = 8;  // loads in flight per thread
+  for (int b = tid; b < 2 * kBoundBins; b += kDenseThreads) (&hist[0][0])[b] = 0;
+  if (tid == 0) s_valid = 0;
+  __syncthreads();
+  // first pass: the top 11 bits of every key, and the finite scores
+  int valid = 0;
+  for (int64_t i0 = tid; i0 < ns; i0 += (int64_t)kDenseThreads * kUn) {
+    float v[kUn];
+#pragma unroll
+    for (int u = 0; u < kUn; ++u) v[u] = i0 + kDenseThreads * u < ns ? row[i0 + kDenseThreads * u] : -INFINITY;
+#pragma unroll
+    for (int u = 0; u < kUn; ++u) {
+      valid += v[u] != -INFINITY;
+      if (i0 + kDenseThreads * u < ns) atomicAdd(&hist[0][order_f32(v[u]) >> 21], 1u);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) valid += __shfl_xor(valid, o);
+  if ((tid & 63) == 0) atomicAdd(&s_valid, valid);
+  __syncthreads();
+  const int nvalid = s_valid;
+  int d0[2] = {-1, -1};
+  uint32_t need[2] = {0, 0};
+  for (int r = 0; r < nr; ++r)
+    if ((int)rank[r] <= nvalid) block_rank_bin(hist[0], rank[r], s_tot, s_out, &d0[r], &need[r]);
+  // second pass: the next 11 bits of the keys under each rank's top bits
+  for (int b = tid; b < 2 * kBoundBins; b += kDenseThreads) (&hist[0][0])[b] = 0;
+  __syncthreads();
+  if (d0[0] >= 0 || d0[1] >= 0) {
+    for (int64_t i0 = tid; i0 < ns; i0 += (int64_t)kDenseThreads * kUn) {
+      float v[kUn];
+#pragma unroll
+      for (int u = 0; u < kUn; ++u) v[u] = i0 + kDenseThreads * u < ns ? row[i0 + kDenseThreads * u] : -INFINITY;
+#pragma unroll
+      for (int u = 0; u < kUn; ++u) {
+        const uint32_t k = order_f32(v[u]);
+        const bool in = i0 + kDenseThreads * u < ns;
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+          if (in && (int)(k >> 21) == d0[r]) atomicAdd(&hist[r][(k >> 10) & (kBoundBins - 1)], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  float tau[2] = {-INFINITY, -INFINITY};
+  for (int r = 0; r < nr; ++r) {
+    if (d0[r] < 0) continue;
+    int d1;
+    uint32_t rest;
+    block_rank_bin(hist[r], need[r], s_tot, s_out, &d1, &rest);
+    const float t = unorder_f32(((uint32_t)d0[r] << 21) | ((uint32_t)d1 << 10));  // the smallest key with these 22 bits
+    tau[r] = t != t ? -INFINITY : t;  // a prefix below every finite score's key
+  }
+  if (tid == 0) {
+    seed[q] = tau[0];
+    if (seed_opt) seed_opt[q] = fmaxf(tau[0], tau[1]);
   }
 }
 
@@ -474,12 +553,29 @@ gv_status dispatch_fmt(int fmt, int dp, const Shape& sh, const ScoreArgs& args, 
 // Sampling strides of the threshold cascade, sparsest first: the sparsest
 // sample (dense scan) holds at least 8 * kappa rows; each next level is 16 times
 // denser; the last entry, 1, is the full scan.  Small databases get no cascade.
-std::vector<int64_t> cascade(int64_t n, int kappa) {
-  std::vector<int64_t> s{1};
-  int64_t top = 0;
-  for (int64_t stride = 16; n / stride >= 8LL * kappa && stride <= (1LL << 24); stride *= 16) top = stride;
-  for (int64_t stride = 16; stride <= top; stride *= 16) s.insert(s.begin(), stride);
-  return s;
+// The cascade's strides, sparsest sample first, ending with the full scan
+// (stride 1): powers of `step` whose samples hold at least 8 kappa rows.
+// Small batches step by 64 when that still leaves a filtering level between
+// the dense sample and the full scan: their scans are bound by HBM, so a
+// sample level costs its launches and select more than its rows, and fewer,
+// wider steps win even though the full scan starts from a looser seed.  Large
+// batches (and databases too small for two 64-fold steps, where the full scan
+// would start from the dense sample's bound) step by 16, which keeps the full
+// scan's survivors few.
+constexpr int64_t kCoarseCascadeM = 256;
+std::vector<int64_t> cascade(int64_t n, int kappa, int64_t m) {
+  auto ladder = [&](int64_t step) {
+    std::vector<int64_t> s{1};
+    int64_t top = 0;
+    for (int64_t stride = step; n / stride >= 8LL * kappa && stride <= (1LL << 24); stride *= step) top = stride;
+    for (int64_t stride = step; stride <= top; stride *= step) s.insert(s.begin(), stride);
+    return s;
+  };
+  if (m <= kCoarseCascadeM) {
+    std::vector<int64_t> s = ladder(64);
+    if (s.size() >= 3) return s;
+  }
+  return ladder(16);
 }
 
 }  // namespace
@@ -559,7 +655,7 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
     return GV_EUNSUPPORTED;
   }
   const Tuning tu = effective_tuning(fmt, p->dp, m, n);
-  p->levels = cascade(n, kappa);
+  p->levels = cascade(n, kappa, m);
   p->has_dense = p->levels.size() > 1;
   const int64_t ntiles = n_pad / kRows;
   // the shapes of every level for a list capacity and a workgroup multiple;
@@ -739,8 +835,6 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
   };
 
   gv_status s = GV_OK;
-  if (p.has_dense && part != Part::Suffix)
-    hipLaunchKernelGGL(k_seed_init, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, m, seed);
   for (size_t li = 0; li < p.levels.size() && s == GV_OK; ++li) {
     const Shape& sh = p.shapes[li];
     sh_cur = sh;
@@ -774,7 +868,7 @@ gv_status run_scan(const gv_index* idx, const ScanPlan& p, uint8_t* ws, const vo
     if (p.has_dense && li == 0) {
       s = dispatch(true);
       if (s == GV_OK)
-        hipLaunchKernelGGL(k_dense_select, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, dense, m, p.ns, kappa,
+        hipLaunchKernelGGL(k_dense_select, dim3((unsigned)m), dim3(kDenseThreads), 0, st, dense, m, p.ns, kappa,
                            seed, p.optimistic ? seed_opt : (float*)nullptr, p.next_rank[0]);
       continue;
     }
@@ -875,10 +969,13 @@ gv_status search_plan(const gv_model* model, const gv_index* idx, int64_t m, int
   sp->off_qhat = o; o = align256(o + eb * m * C * p.dp);
   sp->off_cand = o; o = align256(o + sizeof(int32_t) * m * kappa);
   sp->off_csc = o;  o = align256(o + sizeof(float) * m * kappa);
-  sp->off_scan = o; o = align256(o + p.bytes);
+  // the scan's scratch is free before the first level and after the final
+  // select: S1's partial products and S4's scores use it then
+  const size_t region = std::max(p.bytes, proj_split_bytes(m, (int64_t)model->C * model->d, model->D));
+  sp->off_scan = o; o = align256(o + region);
   sp->scan_bytes = p.bytes;
+  sp->region_bytes = region;
   sp->bytes = std::max<size_t>(o, 256);
-  (void)model;
   return GV_OK;
 }
 
@@ -897,12 +994,12 @@ gv_status search_run(const gv_model* model, const gv_index* idx, const float* Q,
   void* qhat = ws + sp.off_qhat;
   int32_t* cand = (int32_t*)(ws + sp.off_cand);
   float* csc = (float*)(ws + sp.off_csc);
-  GV_TRY(project_impl(model, idx->fmt, Q, m, qc, t, qhat, st, sp.d_search));
+  GV_TRY(project_impl(model, idx->fmt, Q, m, qc, t, qhat, st, sp.d_search, ws + sp.off_scan, sp.region_bytes));
   GV_TRY(run_scan(idx, p, ws + sp.off_scan, qhat, t, m, kappa, cand, csc, st));
   if (sp.stored)
     GV_TRY(rerank_stored_impl(idx, qc, m, cand, kappa, k, out_ids, out_scores, st));
   else
-    GV_TRY(rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st));
+    GV_TRY(rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st, ws + sp.off_scan, sp.region_bytes));
   return GV_OK;
 }
 
@@ -936,7 +1033,7 @@ gv_status search_lazy_impl(const gv_model* model, const gv_index* idx, const flo
   int32_t* cand = (int32_t*)(ws + off_cand);
   float* csc = (float*)(ws + off_csc);
   gv_status s = run_scan(idx, p, ws, nullptr, nullptr, m, kappa, cand, csc, st, &lv);
-  if (s == GV_OK) s = rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st);
+  if (s == GV_OK) s = rerank_impl(idx, Q, m, cand, kappa, k, out_ids, out_scores, st, ws, p.bytes);
   (void)hipFreeAsync(ws, st);
   return s;
 }
@@ -1033,7 +1130,8 @@ gv_status batched_run(std::vector<BatchEntry>& e, int k, int kappa, hipStream_t 
     float* t = (float*)(ws + b.plan.off_t);
     float* qc = (float*)(ws + b.plan.off_qc);
     void* qhat = ws + b.plan.off_qhat;
-    GV_TRY(project_impl(b.model, b.idx->fmt, b.Q, b.m, qc, t, qhat, st, b.plan.d_search));
+    GV_TRY(project_impl(b.model, b.idx->fmt, b.Q, b.m, qc, t, qhat, st, b.plan.d_search, ws + b.plan.off_scan,
+                        b.plan.region_bytes));
     GV_TRY(run_scan(b.idx, plans[i], ws + b.plan.off_scan, qhat, t, b.m, kappa, nullptr, nullptr, st, nullptr,
                     Part::Prefix, &last[i], &last_sh[i]));
   }
@@ -1093,7 +1191,8 @@ gv_status batched_run(std::vector<BatchEntry>& e, int k, int kappa, hipStream_t 
       float* qc = (float*)(ws + b.plan.off_qc);
       GV_TRY(rerank_stored_impl(b.idx, qc, b.m, cand, kappa, k, b.out_ids, b.out_scores, st));
     } else {
-      GV_TRY(rerank_impl(b.idx, b.Q, b.m, cand, kappa, k, b.out_ids, b.out_scores, st));
+      GV_TRY(rerank_impl(b.idx, b.Q, b.m, cand, kappa, k, b.out_ids, b.out_scores, st, ws + b.plan.off_scan,
+                         b.plan.region_bytes));
     }
   }
   for (int j = 0; j < nside; ++j) {
@@ -1118,6 +1217,72 @@ constexpr int kRerankThreads = 1024;
 __device__ void sort_emit(double* s_score, int32_t* s_id, int64_t q, int kappa, int k, int32_t* __restrict__ out_ids,
                           float* __restrict__ out_scores);
 
+// exact <q, x> of four candidate rows (a missing candidate, id outside [0, n),
+// reads row 0 and is dropped by the caller) with FP64 accumulation of exact
+// FP32 x FP32 products; each lane loads its part of the four rows with every
+// load in flight before the first use (the rows are gathered: one memory
+// latency per group of four).  Called by a whole wavefront; every lane gets
+// the four sums.
+__device__ inline void dot4(const float* __restrict__ X, int64_t n, int D, const float* __restrict__ qv,
+                            const int32_t (&id)[4], bool vec, double (&acc)[4]) {
+  const int lane = threadIdx.x & 63;
+  const float* x[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    x[u] = X + ((id[u] >= 0 && id[u] < n) ? (int64_t)id[u] : 0) * D;
+    acc[u] = 0.0;
+  }
+  int j0 = 0;
+  if (vec) {
+    constexpr int kChunk = 4;  // float4 groups per lane per pass: 1024 coordinates of a row
+    for (; j0 + 256 * kChunk <= D; j0 += 256 * kChunk) {
+      float4 xv[4][kChunk], qq[kChunk];
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        const int j = j0 + 4 * (lane + 64 * c);
+        qq[c] = *(const float4*)(qv + j);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u][c] = *(const float4*)(x[u] + j);
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc[u] += (double)xv[u][c].x * (double)qq[c].x;
+          acc[u] += (double)xv[u][c].y * (double)qq[c].y;
+          acc[u] += (double)xv[u][c].z * (double)qq[c].z;
+          acc[u] += (double)xv[u][c].w * (double)qq[c].w;
+        }
+    }
+    for (int j = j0 + 4 * lane; j + 4 <= D; j += 256) {
+      const float4 qq = *(const float4*)(qv + j);
+      float4 xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = *(const float4*)(x[u] + j);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc[u] += (double)xv[u].x * (double)qq.x;
+        acc[u] += (double)xv[u].y * (double)qq.y;
+        acc[u] += (double)xv[u].z * (double)qq.z;
+        acc[u] += (double)xv[u].w * (double)qq.w;
+      }
+    }
+  } else {
+    for (int j = lane; j < D; j += 64) {
+      const double qj = (double)qv[j];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += (double)x[u][j] * qj;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    for (int o = 32; o > 0; o >>= 1) acc[u] += __shfl_xor(acc[u], o);
+}
+
+__device__ inline bool rerank_vec(const float* X, int D, const float* Q) {
+  return (D % 4) == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)Q % 16) == 0;
+}
+
 __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restrict__ X, int64_t n, int D,
                                                            const float* __restrict__ Q,
                                                            const int32_t* __restrict__ cand, int kappa, int k,
@@ -1134,72 +1299,60 @@ __global__ __launch_bounds__(kRerankThreads) void k_rerank(const float* __restri
     s_id[i] = 0x7fffffff;
   }
   __syncthreads();
-  // exact <q, x> with FP64 accumulation of exact FP32 x FP32 products; each
-  // lane loads its part of four candidate rows with every load in flight before
-  // the first use (the rows are gathered: one memory latency per group of four)
-  const bool vec = (D % 4) == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)Q % 16) == 0;
+  const bool vec = rerank_vec(X, D, Q);
   for (int c0 = wave * 4; c0 < kappa; c0 += W * 4) {
     int32_t id[4];
-    bool ok[4];
-    const float* x[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      id[u] = (c0 + u < kappa) ? cand[q * kappa + c0 + u] : -1;
-      ok[u] = id[u] >= 0 && id[u] < n;  // a missing candidate (non-finite query scores) is skipped
-      x[u] = X + (ok[u] ? (int64_t)id[u] : 0) * D;
-    }
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    int j0 = 0;
-    if (vec) {
-      constexpr int kChunk = 4;  // float4 groups per lane per pass: 1024 coordinates of a row
-      for (; j0 + 256 * kChunk <= D; j0 += 256 * kChunk) {
-        float4 xv[4][kChunk], qq[kChunk];
+    for (int u = 0; u < 4; ++u) id[u] = (c0 + u < kappa) ? cand[q * kappa + c0 + u] : -1;
+    double acc[4];
+    dot4(X, n, D, qv, id, vec, acc);
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-          const int j = j0 + 4 * (lane + 64 * c);
-          qq[c] = *(const float4*)(qv + j);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) xv[u][c] = *(const float4*)(x[u] + j);
-        }
-#pragma unroll
-        for (int c = 0; c < kChunk; ++c)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            acc[u] += (double)xv[u][c].x * (double)qq[c].x;
-            acc[u] += (double)xv[u][c].y * (double)qq[c].y;
-            acc[u] += (double)xv[u][c].z * (double)qq[c].z;
-            acc[u] += (double)xv[u][c].w * (double)qq[c].w;
-          }
-      }
-      for (int j = j0 + 4 * lane; j + 4 <= D; j += 256) {
-        const float4 qq = *(const float4*)(qv + j);
-        float4 xv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = *(const float4*)(x[u] + j);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          acc[u] += (double)xv[u].x * (double)qq.x;
-          acc[u] += (double)xv[u].y * (double)qq.y;
-          acc[u] += (double)xv[u].z * (double)qq.z;
-          acc[u] += (double)xv[u].w * (double)qq.w;
-        }
-      }
-    } else {
-      for (int j = lane; j < D; j += 64) {
-        const double qj = (double)qv[j];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += (double)x[u][j] * qj;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      double v = acc[u];
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      if (lane == 0 && ok[u]) {
-        s_score[c0 + u] = v;
+    for (int u = 0; u < 4; ++u)
+      if (lane == 0 && id[u] >= 0 && id[u] < n) {  // a missing candidate (non-finite query scores) is skipped
+        s_score[c0 + u] = acc[u];
         s_id[c0 + u] = id[u];
       }
-    }
+  }
+  __syncthreads();
+  sort_emit(s_score, s_id, q, kappa, k, out_ids, out_scores);
+}
+
+// Small batches: one workgroup per query leaves most of the device idle and
+// takes one gathered-row latency per 64 candidates, so the scores are computed
+// by many workgroups per query (kRerankPart candidates each, one round of
+// loads) into FP64 scratch, and sorted by a second kernel.  Same arithmetic as
+// k_rerank, same results.
+constexpr int kRerankPart = 16;
+constexpr int64_t kRerankSplitM = 256;
+__global__ __launch_bounds__(256) void k_rerank_part(const float* __restrict__ X, int64_t n, int D,
+                                                     const float* __restrict__ Q, const int32_t* __restrict__ cand,
+                                                     int kappa, double* __restrict__ score) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q = blockIdx.y;
+  const int c0 = blockIdx.x * kRerankPart + wave * 4;
+  if (c0 >= kappa) return;
+  int32_t id[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) id[u] = (c0 + u < kappa) ? cand[q * kappa + c0 + u] : -1;
+  double acc[4];
+  dot4(X, n, D, Q + q * D, id, rerank_vec(X, D, Q), acc);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (lane == 0 && c0 + u < kappa) score[q * kappa + c0 + u] = acc[u];
+}
+
+__global__ __launch_bounds__(kRerankThreads) void k_rerank_sort(int64_t n, const int32_t* __restrict__ cand, int kappa,
+                                                                int k, const double* __restrict__ score,
+                                                                int32_t* __restrict__ out_ids,
+                                                                float* __restrict__ out_scores) {
+  __shared__ double s_score[kMaxKappa];
+  __shared__ int32_t s_id[kMaxKappa];
+  const int64_t q = blockIdx.x;
+  for (int i = threadIdx.x; i < kMaxKappa; i += kRerankThreads) {
+    const int32_t id = i < kappa ? cand[q * kappa + i] : -1;
+    const bool ok = id >= 0 && id < n;  // a missing candidate (non-finite query scores) is skipped
+    s_score[i] = ok ? score[q * kappa + i] : -INFINITY;
+    s_id[i] = ok ? id : 0x7fffffff;
   }
   __syncthreads();
   sort_emit(s_score, s_id, q, kappa, k, out_ids, out_scores);
@@ -1321,10 +1474,18 @@ gv_status rerank_stored_impl(const gv_index* idx, const float* qc, int64_t m, co
 }
 
 gv_status rerank_impl(const gv_index* idx, const float* Q, int64_t m, const int32_t* cand, int kappa, int k,
-                      int32_t* out_ids, float* out_scores, hipStream_t st) {
+                      int32_t* out_ids, float* out_scores, hipStream_t st, void* scratch, size_t scratch_bytes) {
   if (m == 0) return GV_OK;
-  hipLaunchKernelGGL(k_rerank, dim3((unsigned)m), dim3(kRerankThreads), 0, st, idx->X, idx->n, idx->D, Q, cand, kappa, k, out_ids,
-                     out_scores);
+  if (scratch && m <= kRerankSplitM && scratch_bytes >= sizeof(double) * (size_t)m * kappa) {
+    double* score = (double*)scratch;
+    hipLaunchKernelGGL(k_rerank_part, dim3((unsigned)((kappa + kRerankPart - 1) / kRerankPart), (unsigned)m),
+                       dim3(256), 0, st, idx->X, idx->n, idx->D, Q, cand, kappa, score);
+    hipLaunchKernelGGL(k_rerank_sort, dim3((unsigned)m), dim3(kRerankThreads), 0, st, idx->n, cand, kappa, k, score,
+                       out_ids, out_scores);
+  } else {
+    hipLaunchKernelGGL(k_rerank, dim3((unsigned)m), dim3(kRerankThreads), 0, st, idx->X, idx->n, idx->D, Q, cand,
+                       kappa, k, out_ids, out_scores);
+  }
   GV_HIP(hipGetLastError());
   return GV_OK;
 }

@@ -43,9 +43,12 @@ CASES = {
     # large enough for the threshold cascade: dense sample, pilot scan, full scan
     "n300k": (106, 64, 4, 300_000, 2_000, 32, 4, 40, 50),
     # the benchmark's reduced length (d = 160) and kappa = 200 on a database with two
-    # cascade levels below the full scan (every 256th tile dense, every 16th filtered):
-    # the sampled-level and full-scan kernels the benchmark launches at m <= 64
+    # cascade levels below the full scan (every 256th tile dense, every 16th filtered)
     "d160-n420k": (107, 256, 8, 420_000, 4_000, 160, 8, 64, 200),
+    # d = 160 with three levels at small batches (every 4096th tile dense, every
+    # 64th filtered, then the full scan) and four at large ones (4096, 256, 16, 1):
+    # the sampled-level kernels the benchmark launches at m = 1, 64 and 4096
+    "d160-n700k": (110, 256, 8, 700_000, 4_000, 160, 8, 64, 20),
     # the longest reduced rows (12 and 16 KiB tiles in 16-bit storage)
     "d192-C8": (108, 384, 8, 24_000, 4_000, 192, 8, 130, 200),
     "d256-C8": (109, 512, 8, 24_000, 4_000, 256, 8, 130, 200),
@@ -217,6 +220,30 @@ def test_project_large_batch_matches_oracle(gv):
     assert np.allclose(qc[:, :, :d], ref_qc, rtol=2 ** -23, atol=0)
 
 
+@pytest.mark.parametrize("C,d,D,m", [(3, 24, 100, 17), (3, 24, 100, 300), (4, 160, 768, 64), (2, 40, 64, 33)])
+def test_project_mid_batches_match_oracle(gv, C, d, D, m):
+    """S1 for batches between the few-query path and the tiled GEMM (16 queries x
+    16 rows per workgroup, D cut into 16 runs): ragged query and row tiles, and
+    D not a multiple of 16 (the last runs are partly or wholly past D).  q_c is
+    the oracle's fl32 of the FP64 product wherever FP64 summation order cannot
+    flip the rounding, and within one FP32 ulp everywhere; the padding is zero."""
+    _say(f"[project mid] C{C} d{d} D{D} m{m}")
+    rng = np.random.default_rng(1000 + m + D)
+    mu = rng.standard_normal((C, D))
+    mu /= np.linalg.norm(mu, axis=1, keepdims=True)
+    A = rng.standard_normal((C, d, D)) / np.sqrt(D)
+    B = rng.standard_normal((C, d, D)) / np.sqrt(D)
+    Q = rng.standard_normal((m, D)).astype(np.float32)
+    model = gv.model_import(mu, A, B)
+    qc, t, qhat = gv.project(model, "fp16", dev(Q))
+    torch.cuda.synchronize()
+    ref_qc, ref_t, ref_qh = G.project_queries(A, Q, "fp16")
+    qc = qc.cpu().numpy().astype(np.float64)
+    assert np.all(qc[:, :, d:] == 0)
+    assert (qc[:, :, :d] == ref_qc).mean() > 0.9999
+    assert np.allclose(qc[:, :, :d], ref_qc, rtol=2 ** -23, atol=0)
+
+
 # ----------------------------------------------------------------------------- S2 + S3 (+ S4)
 
 REGIMES = [
@@ -234,6 +261,10 @@ REGIMES = [
     ("d160-n420k", 1, "m1"),
     ("d160-n420k", 40, "m40"),
     ("d160-n420k", 64, "m64"),
+    ("d160-n700k", 1, "m1"),
+    ("d160-n700k", 40, "m40"),
+    ("d160-n700k", 64, "m64"),
+    ("d160-n700k", 300, "m300"),
 ]
 
 
@@ -467,7 +498,7 @@ def test_kappa_beyond_ring_staging(gv, fmt):
 
 
 @pytest.mark.parametrize("fmt", ["fp32", "fp16", "bf16"])
-@pytest.mark.parametrize("case,m", [("n300k", 130), ("d160-n420k", 64)])
+@pytest.mark.parametrize("case,m", [("n300k", 130), ("d160-n420k", 64), ("d160-n700k", 64), ("d160-n700k", 300)])
 def test_optimistic_seed_and_repair(gv, case, m, fmt):
     """The full scan starts from an optimistic seed (a higher-ranked score of the
     last sample level) and a repair pass rescans every query that kept fewer than
