@@ -781,7 +781,7 @@ gv_status gv_search_batched(int32_t n_coll, const gv_model* const* models, const
       GV_REQUIRE(m[i] == 0 || (Q[i] && out_ids[i]), "gv_search_batched: NULL query or output");
       if (m[i] > 0) {
         BatchEntry b{md, ix, Q[i], m[i], out_ids[i], out_scores ? out_scores[i] : nullptr, SearchPlan{}, nullptr};
-        GV_TRY(search_plan(md, ix, m[i], kappa, &b.plan));
+        GV_TRY(search_plan(md, ix, m[i], kappa, &b.plan, 0, false, kListBudget));
         b.ws = (uint8_t*)(uintptr_t)ws_bytes;  // offset until the workspace exists
         ws_bytes += (b.plan.bytes + 255) / 256 * 256;
         ent.push_back(b);

@@ -297,15 +297,23 @@ gv_status score_topk_impl(const gv_index* index, const void* qhat, const float* 
                           int kappa, int32_t* cand_ids, float* cand_scores, hipStream_t st, int d_search = 0);
 void keep_pool(int device);
 // one search's scratch, carved from a single workspace (byte offsets)
+// bytes of candidate lists an automatic scan plan may take: any shape
+// (kListBudget), and the many-range shape of a large single search
+// (kListBudgetLarge: more, shorter row ranges keep the workgroups that share a
+// range in step, so its tiles stay in L2); the searches of a batched launch
+// hold their lists at the same time and keep to kListBudget
+constexpr uint64_t kListBudget = 2ull << 30;
+constexpr uint64_t kListBudgetLarge = 12ull << 30;
 struct SearchPlan {
   size_t off_t = 0, off_qc = 0, off_qhat = 0, off_cand = 0, off_csc = 0, off_scan = 0, bytes = 0;
+  uint64_t list_budget = kListBudgetLarge;  // for the many-range shape (search_run re-plans with it)
   size_t scan_bytes = 0;  // scratch of S2/S3 within the workspace (search_run re-plans and checks it)
   size_t region_bytes = 0;  // bytes at off_scan: S2/S3's scratch, earlier S1's partial products, later S4's scores
   int d_search = 0;     // leading coordinates scanned
   bool stored = false;  // rerank from the stored vectors instead of the full-dimension X
 };
 gv_status search_plan(const gv_model* model, const gv_index* index, int64_t m, int kappa, SearchPlan* plan,
-                      int d_search = 0, bool stored = false);
+                      int d_search = 0, bool stored = false, uint64_t list_budget = kListBudgetLarge);
 gv_status search_run(const gv_model* model, const gv_index* index, const float* Q, int64_t m, int k, int kappa,
                      int32_t* out_ids, float* out_scores, const SearchPlan& plan, void* workspace, hipStream_t st);
 // one search of a batched launch sequence, with its own workspace

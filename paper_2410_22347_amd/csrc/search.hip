@@ -312,7 +312,6 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense_select(const float* __r
 // FINAL: the kappa best, sorted, as (ids, scores) (-1 / NaN past the end when
 // fewer exist).  Otherwise: seed[q] = max(seed[q], kappa-th best score).
 constexpr int kSelWin = 4096;
-constexpr uint64_t kListBudget = 2ull << 30;  // bytes of candidate lists an automatic plan may take
 constexpr int kMaxLists = 4096;
 static_assert(kMaxKappa <= kSelWin / 2, "a select window holds the kappa kept keys and as many new ones");
 
@@ -648,7 +647,7 @@ ScanLimits scan_limits(int fmt, int dp, const Shape& sh) {
 // n_pad (segments padded to whole tiles), C clusters, format, stored padded
 // length dps, leading length dp_search scanned.
 gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int d_search, int64_t m, int kappa,
-                         ScanPlan* p) {
+                         ScanPlan* p, uint64_t list_budget = kListBudgetLarge) {
   p->dp = pad_dim(d_search);
   if (p->dp > dps || p->dp > 256) {
     set_error("the scan reads at most the leading 256 stored coordinates (padded), and no more than the index stores");
@@ -699,10 +698,16 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
   bool chosen = false;
   if (tu.cap == 0 && tu.splits == 0) {
     // automatic: the most workgroups (up to eight times the base count) with
-    // the smallest list capacity (at least 512) whose lists fit in kListBudget
+    // the smallest list capacity (at least 512) whose lists fit in kListBudget.
+    // Batches large enough that sixteen times the base count still gives at
+    // most 1024 row ranges (m >= 2048 on 10M rows) first try that shape, with
+    // lists up to list_budget: 3% faster at m = 2048 and 4096 than the eightfold
+    // count, while more ranges were slower at m = 1024
+    auto fits = [&](int cap, uint64_t budget) { return (uint64_t)m * p->Rmax * cap * sizeof(uint64_t) <= budget; };
+    chosen = build(512, 16) == GV_OK && p->Rmax <= 1024 && fits(512, list_budget);
     for (int mul = 8; mul >= 1 && !chosen; mul /= 2)
       for (int cap = 512; cap <= kCap && !chosen; cap *= 2)
-        chosen = build(cap, mul) == GV_OK && (uint64_t)m * p->Rmax * cap * sizeof(uint64_t) <= kListBudget;
+        chosen = build(cap, mul) == GV_OK && fits(cap, kListBudget);
     clear_error();
   }
   if (!chosen) GV_TRY(build(tu.cap > 0 ? tu.cap : kCap, 1));
@@ -761,9 +766,10 @@ gv_status plan_scan_dims(int64_t n, int64_t n_pad, int C, int fmt, int dps, int 
   return GV_OK;
 }
 
-gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int d_search = 0) {
+gv_status plan_scan(const gv_index* idx, int64_t m, int kappa, ScanPlan* p, int d_search = 0,
+                    uint64_t list_budget = kListBudgetLarge) {
   return plan_scan_dims(idx->n_rows, idx->n_pad, idx->C, idx->fmt, idx->dp, d_search > 0 ? d_search : idx->d, m,
-                        kappa, p);
+                        kappa, p, list_budget);
 }
 
 // views made inside the scan (Algorithm 3) instead of qhat/t
@@ -953,15 +959,16 @@ gv_status score_topk_impl(const gv_index* idx, const void* qhat, const float* t,
 // Scratch of one search (S1 views and scales, S2/S3 lists, candidates), carved
 // from one workspace so the sequence runs without allocations.
 gv_status search_plan(const gv_model* model, const gv_index* idx, int64_t m, int kappa, SearchPlan* sp,
-                      int d_search, bool stored) {
+                      int d_search, bool stored, uint64_t list_budget) {
   ScanPlan p;
-  GV_TRY(plan_scan(idx, m, kappa, &p, d_search));
+  GV_TRY(plan_scan(idx, m, kappa, &p, d_search, list_budget));
   if (!stored && !idx->X) {
     set_error("the index keeps no full-dimension vectors: rerank from the stored vectors");
     return GV_EINVAL;
   }
   sp->d_search = d_search;
   sp->stored = stored;
+  sp->list_budget = list_budget;
   const size_t C = idx->C, dp = idx->dp, eb = fmt_bytes(view_fmt(idx->fmt));
   size_t o = 0;
   sp->off_t = o;    o = align256(o + sizeof(float) * m * C);
@@ -984,7 +991,7 @@ gv_status search_run(const gv_model* model, const gv_index* idx, const float* Q,
   if (m == 0) return GV_OK;
   uint8_t* ws = (uint8_t*)workspace;
   ScanPlan p;
-  GV_TRY(plan_scan(idx, m, kappa, &p, sp.d_search));
+  GV_TRY(plan_scan(idx, m, kappa, &p, sp.d_search, sp.list_budget));
   if (p.bytes > sp.scan_bytes) {  // the workspace was sized for another plan (tuning changed in between)
     set_error("internal: the search plan changed after its workspace was sized");
     return GV_EDEVICE;
@@ -1059,7 +1066,7 @@ gv_status batched_run(std::vector<BatchEntry>& e, int k, int kappa, hipStream_t 
   std::vector<Cls> cls;
   std::vector<ScanPlan> plans(ne);
   for (int i = 0; i < ne; ++i) {
-    GV_TRY(plan_scan(e[i].idx, e[i].m, kappa, &plans[i], e[i].plan.d_search));
+    GV_TRY(plan_scan(e[i].idx, e[i].m, kappa, &plans[i], e[i].plan.d_search, e[i].plan.list_budget));
     const Shape& sh = plans[i].shapes.back();
     const int fmt = e[i].idx->fmt, dp = plans[i].dp;
     int c = -1;
