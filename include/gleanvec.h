@@ -279,7 +279,10 @@ gv_status gv_index_rows(const gv_index* index, int64_t* rows);
  *       s_i = s_c * t_{q,c} * <q^_c, x^_i>, FP32 accumulation on the matrix cores;
  *   S3  the kappa best s_i per query, ordered by (s_i desc, id asc);
  *   S4  exact <q, x_i> over the kappa candidates, top k.
- * Scratch memory is taken from the stream-ordered allocator.
+ * Scratch memory is taken from the stream-ordered allocator: the candidate
+ * lists take at most 2 GiB, or 12 GiB for batches whose scan uses many short
+ * row ranges (m >= 2048 on 10M rows: 8 GiB at m = 4096), plus the views;
+ * gv_scan_plan reports the figure for a shape.
  *
  * Errors: GV_EINVAL, GV_ENOTFIT, GV_ENOMEM, GV_EDEVICE.
  */
